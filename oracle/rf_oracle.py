@@ -1,0 +1,257 @@
+"""CPU oracle for the realfast search hot path (test infrastructure only).
+
+THIS IS TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import it.  The product path (the HIP library
+and its Python binding) never calls it and shares no code with it.
+
+It is a plain, slow, obviously correct numpy implementation in float64 /
+complex128 of what the search computes, step by step, in the order of the
+search loop of Law et al. 2018 (section 3.1 and the caption of Figure 2:
+loops over trial dispersion measures and sampling times; each dedispersed,
+time-resampled Stokes I image is thresholded on S/N).  The paper states the
+method in words only; where it is silent the readings used are written next
+to the function that needs them and listed together in the design notes.
+
+Functions and the passages they follow:
+  delay_table   section 2.1 footnote (cold-plasma delay 4.15 ms DM / nu^2)
+  cell_table    sections 2.2 and 3.1 (visibility-domain processing, FFT imaging)
+  dedisperse    section 2.2 (dedispersion in the visibility domain), 3.1
+  resample      section 2.2 (matched filters over pulse widths), Figure 2
+                (loop over trial sampling times)
+  stokes_i      section 3.1 (a Stokes I image per DM and width)
+  grid          section 2.2 item 3 (FFT imaging); gridding itself unstated
+  image         section 3.1 / 3.2 (2-D FFT imaging)
+  image_stats   section 3.1 (point sources above an S/N threshold, ~6 sigma)
+  search        section 3.1 / Figure 2 (the whole loop)
+
+Parity pins live in tests/test_oracle_*.py; every function above is pinned
+there against closed forms, brute force, library special cases or the values
+the paper prints.  Readings that no paper value can pin (edge handling,
+resampling kind, gridding kernel, cell size, sigma estimator) are marked
+"parity unpinned" below: only their internal consistency is checked.
+"""
+import math
+
+import numpy as np
+
+C_LIGHT = 299792458.0          # m/s
+MAD_TO_SIGMA = 1.4826          # 1 / Phi^-1(3/4): MAD of a Gaussian -> sigma
+
+
+class Plan:
+    """Everything the search needs besides the visibilities (the pipeline
+    state of section 3.2: metadata plus preferences define it uniquely)."""
+
+    def __init__(self, freq_ghz, uvw_m, tint_s, dms, widths, npix, du, dv,
+                 kdm=4.15e-3, threshold=6.0, t_begin=0, t_end=None, nint=None):
+        self.freq = np.asarray(freq_ghz, dtype=np.float64)
+        self.uvw = np.asarray(uvw_m, dtype=np.float64)
+        self.tint = float(tint_s)
+        self.dms = np.asarray(dms, dtype=np.float64)
+        self.widths = [int(w) for w in widths]
+        self.npix = int(npix)
+        self.du = float(du)
+        self.dv = float(dv)
+        self.kdm = float(kdm)
+        self.threshold = float(threshold)
+        self.nint = nint
+        self.t_begin = int(t_begin)
+        self.t_end = int(t_end) if t_end is not None else (nint if nint is not None else 1 << 30)
+        self.delays = delay_table(self.freq, self.dms, self.tint, self.kdm)
+        self.iu, self.iv = cell_table(self.uvw, self.freq, self.du, self.dv)
+        self.valid = valid_cells(self.iu, self.iv, self.npix)
+        self.W = int(np.count_nonzero(self.valid))
+
+
+def delay_table(freq_ghz, dms, tint_s, kdm):
+    """Integer dispersion delay, in integrations, of every (DM trial, channel).
+
+    Cold-plasma law (section 2.1 footnote): tau = K DM / nu^2, K = 4.15 ms
+    GHz^2 per pc cm^-3.  Readings: delays are relative to the highest channel
+    (which never moves, so every delay is >= 0); the delay in seconds is
+    rounded to whole integrations with round-half-even.  Each product, sum and
+    quotient below is one IEEE float64 operation in exactly this order:
+        d = rint(((K * DM) * (1/(nu*nu) - 1/(nu_ref*nu_ref))) / t_int)
+    Returns int32 [ndm][nchan].
+    """
+    f = np.asarray(freq_ghz, dtype=np.float64)
+    dm = np.asarray(dms, dtype=np.float64)
+    nu_ref = np.max(f)
+    inv = 1.0 / (f * f)
+    inv_ref = 1.0 / (nu_ref * nu_ref)
+    lag = (kdm * dm)[:, None] * (inv - inv_ref)[None, :]
+    return np.rint(lag / tint_s).astype(np.int32)
+
+
+def cell_table(uvw_m, freq_ghz, du, dv):
+    """Nearest uv cell of every (baseline, channel): (iu, iv) int32 [nbl][nchan].
+
+    u in wavelengths is u_m * nu / c; the cell is rint(u_lambda / du) (round
+    half even), each step one float64 operation in this order:
+        iu = rint(((u_m * (nu_ghz * 1e9)) / c) / du)
+    and likewise for v.  Reading (gridding is not described in the paper):
+    nearest-cell assignment with no convolution kernel, w ignored.
+    """
+    f_hz = np.asarray(freq_ghz, dtype=np.float64) * 1e9
+    u = np.asarray(uvw_m, dtype=np.float64)[:, 0]
+    v = np.asarray(uvw_m, dtype=np.float64)[:, 1]
+    iu = np.rint(((u[:, None] * f_hz[None, :]) / C_LIGHT) / du).astype(np.int32)
+    iv = np.rint(((v[:, None] * f_hz[None, :]) / C_LIGHT) / dv).astype(np.int32)
+    return iu, iv
+
+
+def valid_cells(iu, iv, npix):
+    """A (baseline, channel) pair is imaged iff |iu|, |iv| <= N/2 - 1."""
+    lim = npix // 2 - 1
+    return (np.abs(iu) <= lim) & (np.abs(iv) <= lim)
+
+
+def dedisperse(vis, delay_row):
+    """Visibility-domain dedispersion for one DM trial (section 2.2).
+
+    out[t, b, c, p] = vis[t + d[c], b, c, p] if t + d[c] < T, else 0.
+    Reading (parity unpinned: the paper handles edges with overlapping
+    segments, section 3.2): samples shifted in from past the end of the
+    segment are zero.  Pure data movement; returns complex128.
+    """
+    vis = np.asarray(vis)
+    T = vis.shape[0]
+    out = np.zeros(vis.shape, dtype=np.complex128)
+    for c, d in enumerate(np.asarray(delay_row)):
+        d = int(d)
+        if d < T:
+            out[: T - d, :, c, :] = vis[d:, :, c, :]
+    return out
+
+
+def resample(x, w):
+    """Boxcar resampling to sampling time w (Figure 2 loop over sampling time).
+
+    out[k] = (sum_{j<w} x[k w + j]) / w for k < floor(T / w); the remainder is
+    dropped.  Reading (parity unpinned): a decimating mean, not a sliding one.
+    """
+    T = x.shape[0]
+    K = T // w
+    acc = np.zeros((K,) + x.shape[1:], dtype=np.complex128)
+    for j in range(w):
+        acc += x[j: K * w: w]
+    return acc / w
+
+
+def stokes_i(v):
+    """Stokes I from the polarisation axis (last): mean of the two
+    polarisations, or the single one when npol == 1 (section 3.1)."""
+    if v.shape[-1] == 1:
+        return v[..., 0].astype(np.complex128)
+    return (v[..., 0] + v[..., 1]) / 2.0
+
+
+def grid(vi, iu, iv, valid, npix):
+    """Natural-weight nearest-cell gridding of one Stokes I sample set.
+
+    G[iv mod N, iu mod N] += V_I[b, c] over valid pairs; complex128 [N][N].
+    """
+    G = np.zeros((npix, npix), dtype=np.complex128)
+    np.add.at(G, (np.mod(iv[valid], npix), np.mod(iu[valid], npix)), vi[valid])
+    return G
+
+
+def image(G, W):
+    """Stokes I image from a grid (2-D FFT imaging, section 3.2).
+
+    img[Y, X] = (1/W) Re sum_{iu,iv} G[iv, iu] exp(+2 pi i (iu (X - N/2) +
+    iv (Y - N/2)) / N), i.e. the unnormalised inverse DFT, shifted so the
+    phase centre is pixel (N/2, N/2), divided by the number of gridded
+    samples W.  numpy's inverse FFT is the library step.
+    """
+    N = G.shape[0]
+    F = np.fft.ifft2(G) * (N * N)
+    return np.fft.fftshift(F).real / W
+
+
+def image_stats(img):
+    """(peak, X, Y, sigma, snr) of one image (section 3.1 thresholding).
+
+    peak is the signed maximum; ties go to the lowest Y*N + X.  Reading
+    (parity unpinned): sigma = 1.4826 * lower median of |img| (a median
+    absolute deviation about zero; the image mean is zero because the
+    zero-spacing cell is empty).  snr = peak / sigma, 0 when sigma == 0.
+    """
+    N = img.shape[1]
+    flat = img.ravel()
+    idx = int(np.argmax(flat))
+    peak = float(flat[idx])
+    a = np.abs(flat)
+    k = (a.size - 1) // 2
+    med = float(np.partition(a, k)[k])
+    sigma = MAD_TO_SIGMA * med
+    snr = peak / sigma if sigma != 0.0 else 0.0
+    return peak, idx % N, idx // N, sigma, snr
+
+
+def make_image(vis_int, plan):
+    """Image of one resampled integration vis_int [nbl][nchan][npol]."""
+    vi = stokes_i(vis_int)
+    G = grid(vi, plan.iu, plan.iv, plan.valid, plan.npix)
+    return image(G, plan.W)
+
+
+def search(vis, plan, select=None, keep_images=False):
+    """The search loop of Figure 2: for each DM trial dedisperse, for each
+    sampling time resample, image every integration and threshold it.
+
+    vis: complex [T][nbl][nchan][npol] (or float16 [..., 2] storage).
+    select: optional set of (dm_idx, width_idx, k) to image; default all.
+    Returns (stats, candidates, images):
+      stats: dict (i, j, k) -> (peak, X, Y, sigma, snr)
+      candidates: list of (i, j, t_int, X, Y, snr, peak, sigma) for images
+        with snr > threshold and t_begin <= k*w < t_end, in (i, j, k) order.
+    """
+    vis = as_complex(vis)
+    T = vis.shape[0]
+    stats, cands, images = {}, [], {}
+    dm_set = range(len(plan.dms)) if select is None else sorted({s[0] for s in select})
+    for i in dm_set:
+        dd = dedisperse(vis, plan.delays[i])
+        for j, w in enumerate(plan.widths):
+            if select is not None and not any(s[0] == i and s[1] == j for s in select):
+                continue
+            rs = resample(dd, w)
+            for k in range(T // w):
+                if select is not None and (i, j, k) not in select:
+                    continue
+                img = make_image(rs[k], plan)
+                st = image_stats(img)
+                stats[(i, j, k)] = st
+                if keep_images:
+                    images[(i, j, k)] = img
+                peak, x, y, sigma, snr = st
+                t_int = k * w
+                if snr > plan.threshold and plan.t_begin <= t_int < plan.t_end:
+                    cands.append((i, j, t_int, x, y, snr, peak, sigma))
+    return stats, cands, images
+
+
+def as_complex(vis):
+    """complex64/complex128 arrays pass through; float16 [..., 2] storage is
+    widened exactly to complex128."""
+    vis = np.asarray(vis)
+    if np.iscomplexobj(vis):
+        return vis
+    if vis.dtype == np.float16 and vis.shape[-1] == 2:
+        return vis[..., 0].astype(np.float64) + 1j * vis[..., 1].astype(np.float64)
+    raise TypeError("visibilities must be complex or float16 [..., 2]")
+
+
+def is_marginal(img, snr, threshold, tol):
+    """Margin guard for candidate parity: an image whose S/N is within 10 tol
+    (relative) of the threshold, or whose top two pixels are within 10 tol
+    (relative) of each other, may legitimately flip between two correct
+    float implementations."""
+    if abs(snr - threshold) < 10 * tol * threshold:
+        return True
+    flat = np.sort(img.ravel())
+    top, second = flat[-1], flat[-2]
+    if top == 0.0:
+        return True
+    return (top - second) / abs(top) < 10 * tol

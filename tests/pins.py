@@ -1,0 +1,337 @@
+"""Pins for the CPU oracle: checks against values fixed by the paper or by
+mathematics, never against the oracle's own formula.
+
+Each check takes an implementation namespace `o` (the oracle module, or a copy
+with a planted mistake) and raises AssertionError when the implementation is
+wrong.  test_oracle_pins.py runs them on the oracle; test_oracle_mutants.py
+runs them on oracles with planted mistakes and requires that they fail.
+"""
+import json
+import math
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def paper_values():
+    with open(os.path.join(GOLDEN, "paper_values.json")) as f:
+        return json.load(f)
+
+
+def centres(lo, hi, n):
+    return lo + (np.arange(n) + 0.5) * (hi - lo) / n
+
+
+# ---------------------------------------------------------------- delay table
+
+def check_delay_law(o):
+    """The printed law: tau = 4.15 ms DM / nu^2 (section 2.1 footnote).
+    Against an effectively infinite reference frequency, with 1 us
+    integrations, DM 1 at 1 GHz is 4150 us, DM 100 at 2 GHz is 103750 us and
+    DM 7 at 0.5 GHz is 4 * 7 * 4150 us."""
+    pv = paper_values()["dispersion_law"]
+    k = pv["delay_ms_per_dm_at_1ghz"] * 1e-3
+    f = np.array([1.0, 2.0, 0.5, 1e9])
+    d = o.delay_table(f, np.array([1.0, 100.0, 7.0]), 1e-6, k)
+    assert d.shape == (3, 4)
+    assert int(d[0, 0]) == 4150, d
+    assert int(d[1, 1]) == 103750, d
+    assert int(d[2, 2]) == 4 * 7 * 4150, d
+    assert (d[:, 3] == 0).all()
+
+
+def check_delay_properties(o):
+    f = centres(1.0, 2.0, 64)
+    dms = np.linspace(0, 500, 11)
+    d = o.delay_table(f, dms, 0.005, 4.15e-3)
+    assert d.dtype == np.int32
+    assert (d[0] == 0).all(), "DM = 0 must not shift anything"
+    assert (d[:, -1] == 0).all(), "the top channel is the reference"
+    assert (d >= 0).all()
+    assert (np.diff(d, axis=1) <= 0).all(), "delay must not grow with frequency"
+    assert (np.diff(d, axis=0) >= 0).all(), "delay must not shrink with DM"
+
+
+def check_delay_hand_values(o):
+    hv = paper_values()["hand_values"]
+    t = hv["tiny_dm100_chan0"]
+    d = o.delay_table(centres(t["f_lo_ghz"], t["f_hi_ghz"], t["nchan"]),
+                      np.array([t["dm"]]), t["tint_s"], 4.15e-3)
+    assert int(d[0, t["chan"]]) == t["delay"], d[0, :4]
+    for key in ("survey_dm1000_max", "large_dm3000_max"):
+        s = hv[key]
+        d = o.delay_table(centres(s["f_lo_ghz"], s["f_hi_ghz"], s["nchan"]),
+                          np.array([s["dm"]]), s["tint_s"], 4.15e-3)
+        assert int(d.max()) == s["delay_max"], (key, int(d.max()))
+
+
+def check_delay_rounding(o):
+    """Whole-integration rounding is round-half-even: with K DM = 1.25 s GHz^2,
+    nu = 2 GHz against an infinite reference and t_int = 0.125 s the exact
+    delay is 2.5 integrations -> 2; with K DM = 1.75 it is 3.5 -> 4."""
+    f = np.array([2.0, 1e150])
+    d = o.delay_table(f, np.array([1.25, 1.75]), 0.125, 1.0)
+    assert int(d[0, 0]) == 2 and int(d[1, 0]) == 4, d
+
+
+def check_sweep_example(o):
+    """Section 3.2: DM 2000 over 256 MHz at 1.4 GHz sweeps 'roughly 2 s'."""
+    s = paper_values()["sweep_example"]
+    lo = s["centre_ghz"] - s["bandwidth_mhz"] / 2000.0
+    hi = s["centre_ghz"] + s["bandwidth_mhz"] / 2000.0
+    d = o.delay_table(np.array([lo, hi]), np.array([s["dm"]]), 1e-3, 4.15e-3)
+    sweep = d[0, 0] * 1e-3
+    assert 0.7 * s["approx_sweep_s"] < sweep < 1.05 * s["approx_sweep_s"], sweep
+
+
+# ---------------------------------------------------------------- cell table
+
+def check_cells(o):
+    """Hand values: a 1000 m east baseline at 1.5 GHz spans
+    1000 * 1.5e9 / 299792458 = 5003.46 wavelengths -> cell 50 at du = 100;
+    a 250 m north baseline at the same frequency is 1250.87 wavelengths ->
+    cell 13 at dv = 100 (while u is 0)."""
+    uvw = np.array([[1000.0, 0.0, 0.0], [0.0, 250.0, 0.0], [-1000.0, -250.0, 0.0]])
+    iu, iv = o.cell_table(uvw, np.array([1.5, 3.0]), 100.0, 100.0)
+    assert iu.shape == (3, 2)
+    assert int(iu[0, 0]) == 50 and int(iv[0, 0]) == 0
+    assert int(iu[1, 0]) == 0 and int(iv[1, 0]) == 13
+    assert int(iu[2, 0]) == -50 and int(iv[2, 0]) == -13
+    assert int(iu[0, 1]) == 100 and int(iv[1, 1]) == 25  # 10006.9 -> 100; 2501.7 -> 25
+    assert o.valid_cells(np.array([63, 64, -63, -64]), np.array([0, 0, 0, 0]), 128).tolist() == [True, False, True, False]
+
+
+# ---------------------------------------------------------------- dedispersion
+
+def check_dedisperse(o):
+    rng = np.random.default_rng(11)
+    T, B, C, P = 12, 3, 5, 2
+    vis = rng.standard_normal((T, B, C, P)) + 1j * rng.standard_normal((T, B, C, P))
+    assert np.array_equal(o.dedisperse(vis, np.zeros(C, np.int32)), vis), "DM = 0 is the identity"
+    d = np.array([4, 3, 2, 0, 13], np.int32)
+    # an impulse arriving at t0 + d[c] in every channel lands at t0
+    imp = np.zeros((T, B, C, P), complex)
+    t0 = 5
+    for c in range(C):
+        if t0 + d[c] < T:
+            imp[t0 + d[c], :, c, :] = 1.0
+    out = o.dedisperse(imp, d)
+    for c in range(C):
+        col = out[:, 0, c, 0]
+        if t0 + d[c] < T:
+            assert col[t0] == 1.0 and np.count_nonzero(col) == 1, (c, col)
+        else:
+            assert np.count_nonzero(col) == 0
+    # what moves in from past the end is zero; nothing else is touched
+    out = o.dedisperse(vis, d)
+    assert (out[T - 4:, :, 0, :] == 0).all()
+    assert np.array_equal(out[: T - 4, :, 0, :], vis[4:, :, 0, :])
+    assert (out[:, :, 4, :] == 0).all()
+    assert np.array_equal(out[:, :, 3, :], vis[:, :, 3, :])
+
+
+# ---------------------------------------------------------------- resampling
+
+def check_resample(o):
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((13, 2, 3, 2)) + 1j * rng.standard_normal((13, 2, 3, 2))
+    assert np.array_equal(o.resample(x, 1), x)
+    r4 = o.resample(x, 4)
+    assert r4.shape == (3, 2, 3, 2), "the remainder is dropped"
+    # a linear ramp t -> mean over [k w, (k+1) w) is k w + (w - 1)/2
+    ramp = np.arange(13, dtype=float)[:, None, None, None] * np.ones((1, 2, 3, 2))
+    r = o.resample(ramp.astype(complex), 4)
+    assert np.allclose(r[:, 0, 0, 0].real, [1.5, 5.5, 9.5], rtol=0, atol=1e-15)
+    assert np.allclose(o.resample(np.full((8, 1, 1, 1), 3.0 + 2j), 8), 3.0 + 2j)
+    # resampling twice by 2 equals resampling by 4
+    assert np.allclose(o.resample(o.resample(x, 2), 2), r4, rtol=0, atol=1e-14)
+    # flux is conserved over the kept samples
+    assert np.allclose(r4.sum(axis=0) * 4, x[:12].sum(axis=0), rtol=0, atol=1e-12)
+
+
+def check_stokes(o):
+    v = np.zeros((2, 3, 2), complex)
+    v[..., 0] = 1 + 2j
+    v[..., 1] = 3 - 4j
+    assert np.allclose(o.stokes_i(v), 2 - 1j)
+    assert np.allclose(o.stokes_i(v[..., :1]), 1 + 2j)
+
+
+# ---------------------------------------------------------------- gridding
+
+def check_grid(o):
+    N = 16
+    iu = np.array([[3, -2], [3, 7]])
+    iv = np.array([[-5, 0], [-5, 9]])
+    valid = o.valid_cells(iu, iv, N)
+    assert valid.tolist() == [[True, True], [True, False]]
+    vi = np.array([[1 + 1j, 2.0], [0.5j, 100.0]])
+    G = o.grid(vi, iu, iv, valid, N)
+    assert G.shape == (N, N)
+    assert G[N - 5, 3] == 1 + 1.5j, "two samples in one cell add; negative v wraps"
+    assert G[0, N - 2] == 2.0, "negative u wraps to column N - 2"
+    assert np.count_nonzero(G) == 2
+    assert np.isclose(G.sum(), (1 + 1j) + 2 + 0.5j), "dropped samples do not reach the grid"
+
+
+# ---------------------------------------------------------------- imaging
+
+def _dft_image(vi, iu, iv, N, W):
+    """Brute force: direct sum over samples of the image definition."""
+    X = np.arange(N) - N / 2
+    img = np.zeros((N, N))
+    for a, u, v in zip(vi, iu, iv):
+        ph = 2 * np.pi * (u * X[None, :] + v * X[:, None]) / N
+        img += (a * np.exp(1j * ph)).real
+    return img / W
+
+
+def check_image_dft(o):
+    """FFT imaging equals a brute-force direct DFT of the samples (N <= 64)."""
+    rng = np.random.default_rng(13)
+    for N in (16, 32, 64):
+        n = 40
+        iu = rng.integers(-N // 2 + 1, N // 2, n)
+        iv = rng.integers(-N // 2 + 1, N // 2, n)
+        vi = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        W = n
+        G = o.grid(vi, iu, iv, np.ones(n, bool), N)
+        img = o.image(G, W)
+        ref = _dft_image(vi, iu, iv, N, W)
+        assert np.max(np.abs(img - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref))), N
+
+
+def check_image_single_cell(o):
+    """One unit sample at cell (iu, iv) = (3, -5) images to
+    cos(2 pi (3 (X - N/2) - 5 (Y - N/2)) / N) / W (orientation and sign)."""
+    N = 32
+    G = np.zeros((N, N), complex)
+    G[(-5) % N, 3] = 1.0
+    img = o.image(G, 7)
+    X = np.arange(N) - N / 2
+    ref = np.cos(2 * np.pi * (3 * X[None, :] - 5 * X[:, None]) / N) / 7
+    assert np.allclose(img, ref, rtol=0, atol=1e-13)
+    # a quarter-turn phase makes it -sin(...)
+    G[(-5) % N, 3] = 1j
+    ref = -np.sin(2 * np.pi * (3 * X[None, :] - 5 * X[:, None]) / N) / 7
+    assert np.allclose(o.image(G, 7), ref, rtol=0, atol=1e-13)
+
+
+def check_image_point_source(o):
+    """A source at the phase centre (V = A on every sample) images to A at
+    pixel (N/2, N/2), which is the global maximum."""
+    rng = np.random.default_rng(14)
+    N = 64
+    n = 300
+    iu = rng.integers(-N // 2 + 1, N // 2, n)
+    iv = rng.integers(-N // 2 + 1, N // 2, n)
+    A = 0.37
+    img = o.image(o.grid(np.full(n, A, complex), iu, iv, np.ones(n, bool), N), n)
+    assert abs(img[N // 2, N // 2] - A) < 1e-14
+    assert np.argmax(img) == (N // 2) * N + N // 2
+
+
+def check_image_parseval(o):
+    """sum img^2 = N^2/(2 W^2) (sum |G|^2 + Re sum G[k] G[-k]); sum img =
+    N^2 Re G[0, 0] / W."""
+    rng = np.random.default_rng(15)
+    N, W = 32, 9
+    G = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    img = o.image(G, W)
+    Gm = np.roll(np.flip(G, axis=(0, 1)), 1, axis=(0, 1))  # G[-k]
+    lhs = float((img ** 2).sum())
+    rhs = N * N / (2 * W * W) * (float((np.abs(G) ** 2).sum()) + float((G * Gm).sum().real))
+    assert abs(lhs - rhs) < 1e-10 * rhs
+    assert abs(img.sum() - N * N * G[0, 0].real / W) < 1e-9
+
+
+def check_image_offset_source(o):
+    """A source at pixel (X0, Y0), simulated with exact phases and gridded to
+    the nearest cell, peaks at (X0, Y0) above 0.98 of its flux."""
+    import rfgen
+    N = 128
+    uvw = rfgen.baseline_uvw(rfgen.y_array_positions(27))
+    f = centres(1.0, 2.0, 32)
+    du = rfgen.default_cell_size(uvw, f, N)
+    iu, iv = o.cell_table(uvw, f, du, du)
+    valid = o.valid_cells(iu, iv, N)
+    for X0, Y0 in ((N // 2 + 5, N // 2 - 3), (N // 2 - 8, N // 2 + 7)):
+        l, m = rfgen.pixel_to_lm(X0, Y0, N, du, du)
+        ul = uvw[:, 0:1] * f[None, :] * 1e9 / rfgen.C_LIGHT
+        vl = uvw[:, 1:2] * f[None, :] * 1e9 / rfgen.C_LIGHT
+        vi = 0.5 * np.exp(-2j * np.pi * (ul * l + vl * m))
+        img = o.image(o.grid(vi, iu, iv, valid, N), int(valid.sum()))
+        y, x = divmod(int(np.argmax(img)), N)
+        assert (x, y) == (X0, Y0), (x, y)
+        assert img[y, x] > 0.98 * 0.5
+
+
+def check_image_linear(o):
+    rng = np.random.default_rng(16)
+    N = 16
+    G1 = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    G2 = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    assert np.allclose(o.image(2 * G1 - G2, 5), 2 * o.image(G1, 5) - o.image(G2, 5), atol=1e-12)
+
+
+# ---------------------------------------------------------------- statistics
+
+def check_stats(o):
+    rng = np.random.default_rng(17)
+    img = rng.standard_normal((32, 32))
+    img[7, 9] = 50.0
+    img[20, 3] = 50.0   # tie: the lower flat index (row 7) wins
+    peak, x, y, sigma, snr = o.image_stats(img)
+    assert (peak, x, y) == (50.0, 9, 7)
+    a = np.sort(np.abs(img.ravel()))
+    assert sigma == 1.4826 * a[(a.size - 1) // 2], "lower median of |img|"
+    assert snr == peak / sigma
+    # a negative extreme is not a peak; all-zero images have S/N 0
+    img2 = -np.abs(img)
+    img2[0, 0] = 1.0
+    assert o.image_stats(img2)[:3] == (1.0, 0, 0)
+    assert o.image_stats(np.zeros((8, 8)))[4] == 0.0
+    # S/N is scale free
+    assert abs(o.image_stats(3 * img)[4] - snr) < 1e-12 * snr
+
+
+def check_noise_sigma(o):
+    """Unit complex noise per polarisation, averaged over 2 polarisations and
+    w samples, gives image noise (2 w W)^-1/2 (MAD estimate within 5%)."""
+    import rfgen
+    N, nchan = 128, 32
+    uvw = rfgen.baseline_uvw(rfgen.y_array_positions(27))
+    f = centres(1.0, 2.0, nchan)
+    du = rfgen.default_cell_size(uvw, f, N)
+    iu, iv = o.cell_table(uvw, f, du, du)
+    valid = o.valid_cells(iu, iv, N)
+    W = int(valid.sum())
+    vis = rfgen.noise_vis(21, 8, uvw.shape[0], nchan, 2)
+    for w in (1, 2):
+        rs = o.resample(vis.astype(np.complex128), w)
+        sig = [o.image_stats(o.image(o.grid(o.stokes_i(rs[k]), iu, iv, valid, N), W))[3]
+               for k in range(rs.shape[0])]
+        pred = (2 * w * W) ** -0.5
+        assert abs(np.mean(sig) / pred - 1) < 0.05, (w, np.mean(sig), pred)
+
+
+# ---------------------------------------------------------------- layout
+
+def check_table1_layout():
+    """Table 1 rates follow from 351 baselines x channels x 2 pols x 8-byte
+    complex64 per integration: the layout the search consumes."""
+    t = paper_values()["table1"]
+    for row in t["rows"]:
+        rate = t["baselines"] * row["channels"] * t["npol"] * np.dtype(np.complex64).itemsize / (row["tint_ms"] * 1e-3) / 1e6
+        assert abs(rate / row["rate_mb_s"] - 1) < 0.05, (row, rate)
+
+
+ALL_CHECKS = [
+    check_delay_law, check_delay_properties, check_delay_hand_values, check_delay_rounding,
+    check_sweep_example, check_cells, check_dedisperse, check_resample, check_stokes,
+    check_grid, check_image_dft, check_image_single_cell, check_image_point_source,
+    check_image_parseval, check_image_offset_source, check_image_linear, check_stats,
+    check_noise_sigma,
+]

@@ -1,0 +1,170 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each mutant copies the oracle's namespace and replaces one function with a
+plausibly wrong version (a dropped term, a wrong sign, a swapped index, a
+transposed operand).  At least one pin must reject every mutant; otherwise the
+pins would not be evidence that the oracle is right.
+"""
+import types
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import rf_oracle as ro
+import pins
+
+
+def mutant(**repl):
+    ns = types.SimpleNamespace(**{k: getattr(ro, k) for k in dir(ro) if not k.startswith("__")})
+    for k, v in repl.items():
+        setattr(ns, k, v)
+    return ns
+
+
+def _delay_inv_nu(freq, dms, tint, kdm):             # 1/nu instead of 1/nu^2
+    f = np.asarray(freq, float)
+    lag = (kdm * np.asarray(dms, float))[:, None] * (1.0 / f - 1.0 / f.max())[None, :]
+    return np.rint(lag / tint).astype(np.int32)
+
+
+def _delay_floor(freq, dms, tint, kdm):              # floor instead of rint
+    f = np.asarray(freq, float)
+    lag = (kdm * np.asarray(dms, float))[:, None] * (1.0 / (f * f) - 1.0 / (f.max() ** 2))[None, :]
+    return np.floor(lag / tint).astype(np.int32)
+
+
+def _delay_ref_low(freq, dms, tint, kdm):            # reference at the bottom channel
+    f = np.asarray(freq, float)
+    lag = (kdm * np.asarray(dms, float))[:, None] * (1.0 / (f.min() ** 2) - 1.0 / (f * f))[None, :]
+    return np.rint(lag / tint).astype(np.int32)
+
+
+def _dedisperse_backwards(vis, d):                   # t - d instead of t + d
+    T = vis.shape[0]
+    out = np.zeros(vis.shape, complex)
+    for c, dd in enumerate(d):
+        dd = int(dd)
+        if dd < T:
+            out[dd:, :, c, :] = vis[: T - dd, :, c, :]
+    return out
+
+
+def _resample_sum(x, w):                             # sum instead of mean
+    return ro.resample(x, w) * w
+
+
+def _resample_sliding(x, w):                         # sliding boxcar
+    K = x.shape[0] - w + 1
+    return np.stack([x[k:k + w].mean(axis=0) for k in range(K)])
+
+
+def _stokes_sum(v):                                  # dropped 1/2
+    return v[..., 0] + v[..., 1] if v.shape[-1] == 2 else v[..., 0]
+
+
+def _grid_transposed(vi, iu, iv, valid, N):          # u and v swapped
+    return ro.grid(vi, iv, iu, valid, N)
+
+
+def _grid_no_wrap(vi, iu, iv, valid, N):             # negative cells clipped
+    G = np.zeros((N, N), complex)
+    m = valid & (iu >= 0) & (iv >= 0)
+    np.add.at(G, (iv[m], iu[m]), vi[m])
+    return G
+
+
+def _image_forward(G, W):                            # forward instead of inverse DFT
+    N = G.shape[0]
+    return np.fft.fftshift(np.fft.fft2(G)).real / W
+
+
+def _image_noshift(G, W):                            # fftshift dropped
+    N = G.shape[0]
+    return (np.fft.ifft2(G) * N * N).real / W
+
+
+def _image_no_norm(G, W):                            # 1/W dropped
+    N = G.shape[0]
+    return np.fft.fftshift(np.fft.ifft2(G) * N * N).real
+
+
+def _image_transposed(G, W):                         # image transposed
+    return ro.image(G, W).T
+
+
+def _image_abs(G, W):                                # |.| instead of Re
+    N = G.shape[0]
+    return np.abs(np.fft.fftshift(np.fft.ifft2(G) * N * N)) / W
+
+
+def _stats_mean(img):                                # sigma from the mean |img|
+    p, x, y, _, _ = ro.image_stats(img)
+    s = 1.4826 * float(np.mean(np.abs(img)))
+    return p, x, y, s, (p / s if s else 0.0)
+
+
+def _stats_std(img):                                 # sigma = standard deviation
+    p, x, y, _, _ = ro.image_stats(img)
+    s = float(np.std(img))
+    return p, x, y, s, (p / s if s else 0.0)
+
+
+def _stats_absmax(img):                              # peak of |img|
+    N = img.shape[1]
+    idx = int(np.argmax(np.abs(img)))
+    _, _, _, s, _ = ro.image_stats(img)
+    p = float(np.abs(img).ravel()[idx])
+    return p, idx % N, idx // N, s, (p / s if s else 0.0)
+
+
+def _stats_xy_swapped(img):                          # X and Y swapped
+    p, x, y, s, snr = ro.image_stats(img)
+    return p, y, x, s, snr
+
+
+def _cells_no_freq(uvw, freq, du, dv):               # frequency dropped from u
+    u = np.asarray(uvw)[:, 0:1] * np.ones((1, len(freq)))
+    v = np.asarray(uvw)[:, 1:2] * np.ones((1, len(freq)))
+    return np.rint(u / du).astype(np.int32), np.rint(v / dv).astype(np.int32)
+
+
+MUTANTS = {
+    "delay 1/nu": dict(delay_table=_delay_inv_nu),
+    "delay floor": dict(delay_table=_delay_floor),
+    "delay ref at bottom": dict(delay_table=_delay_ref_low),
+    "dedisperse backwards": dict(dedisperse=_dedisperse_backwards),
+    "resample sum": dict(resample=_resample_sum),
+    "resample sliding": dict(resample=_resample_sliding),
+    "stokes sum": dict(stokes_i=_stokes_sum),
+    "grid transposed": dict(grid=_grid_transposed),
+    "grid no wrap": dict(grid=_grid_no_wrap),
+    "image forward": dict(image=_image_forward),
+    "image no shift": dict(image=_image_noshift),
+    "image no 1/W": dict(image=_image_no_norm),
+    "image transposed": dict(image=_image_transposed),
+    "image abs": dict(image=_image_abs),
+    "sigma mean": dict(image_stats=_stats_mean),
+    "sigma std": dict(image_stats=_stats_std),
+    "peak abs": dict(image_stats=_stats_absmax),
+    "stats xy swapped": dict(image_stats=_stats_xy_swapped),
+    "cells no freq": dict(cell_table=_cells_no_freq),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name):
+    o = mutant(**MUTANTS[name])
+    failed = []
+    for check in pins.ALL_CHECKS:
+        try:
+            check(o)
+        except (AssertionError, ValueError, IndexError):
+            failed.append(check.__name__)
+    assert failed, f"no pin catches the planted mistake '{name}'"
+
+
+def test_unmutated_passes_everything():
+    o = mutant()
+    for check in pins.ALL_CHECKS:
+        check(o)
