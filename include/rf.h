@@ -1,0 +1,231 @@
+/*
+ * rf.h -- C ABI of librf, the MI355X (gfx950) realfast search hot path.
+ *
+ * The search (Law et al. 2018, section 3.1 and Figure 2) loops over trial
+ * dispersion measures and trial sampling times.  For each (DM, width) it
+ * dedisperses the visibilities, boxcar-resamples them in time, forms a Stokes
+ * I image of every resampled integration by gridding and a 2-D FFT, and keeps
+ * images whose peak exceeds a threshold in units of the image noise.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers named h_* are host memory, d_* are device memory on the current
+ * HIP device.  All d_* buffers are owned by the caller; the library never
+ * allocates device memory.  A plan's device tables live in a caller-provided
+ * buffer (rf_plan_create).  Workspaces are caller-provided too; their sizes
+ * come from rf_workspace_bytes.
+ *
+ * `stream` is a hipStream_t passed as void* (NULL is the null stream).  Every
+ * call except rf_plan_create / rf_get_* enqueues its kernels on `stream` and
+ * returns at once.  The returned status covers the host-side checks only; on
+ * any error nothing has been enqueued.  Faults found on the device are
+ * reported as data (candidate overflow via the true count in *d_ncand).
+ *
+ * Visibility layout: [nint][nbl][nchan][npol] row-major, each element a
+ * complex number stored as interleaved (re, im):
+ *   RF_CF32  two float32 (8 bytes),  RF_CF16  two IEEE binary16 (4 bytes).
+ * Arithmetic is float32 in every kernel whatever the storage type; float64
+ * is used only for the dispersion-delay and uv-cell arguments.
+ *
+ * Plans are immutable once created; concurrent calls on distinct streams
+ * with distinct output buffers are safe.  No C++ exception crosses the ABI.
+ */
+#ifndef RF_H
+#define RF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rf_status;
+#define RF_OK             0
+#define RF_EINVAL        -1  /* null pointer or malformed argument            */
+#define RF_ESHAPE        -2  /* buffer or count does not match the plan        */
+#define RF_ERANGE        -3  /* value out of the supported range               */
+#define RF_EWORKSPACE    -4  /* workspace or table buffer too small            */
+#define RF_EHIP          -5  /* the HIP runtime reported an error              */
+#define RF_EUNSUPPORTED  -6  /* valid request this build does not implement    */
+
+enum { RF_CF32 = 0, RF_CF16 = 1 };
+
+/* Workspace queries (rf_workspace_bytes `op`). */
+enum { RF_OP_IMAGE = 1, RF_OP_SEARCH = 2, RF_OP_SEGMENT = 3 };
+
+/*
+ * Plan description: the pipeline state of section 3.2 (observation metadata
+ * plus search preferences).  All arrays are host memory and are copied.
+ *
+ *  nint, nbl, nchan, npol  segment shape; npol in {1, 2}; nbl = number of
+ *                          antenna pairs (section 2.2).
+ *  vis_dtype               RF_CF32 or RF_CF16 storage of the segment.
+ *  tint_s                  integration time, seconds (> 0).
+ *  freq_ghz[nchan]         channel centre frequencies, GHz (> 0).
+ *  uvw_m[nbl][3]           baseline coordinates, metres, constant over the
+ *                          segment; w is ignored (zenith phase centre).
+ *  dm[ndm]                 trial dispersion measures, pc cm^-3 (>= 0).
+ *  width[nwidth]           trial boxcar widths, integrations (1..nint).
+ *  npix                    image side N, a power of two in [64, 2048].
+ *  du, dv                  uv cell size, wavelengths (> 0).
+ *  kdm                     dispersion constant, s GHz^2 per pc cm^-3; the
+ *                          section 2.1 footnote prints 4.15e-3.
+ *  threshold               S/N threshold (section 3.1: typically 6).
+ *  t_begin, t_end          candidates are kept only if their start
+ *                          integration t = k * width is in [t_begin, t_end).
+ */
+typedef struct rf_plan_desc {
+  int32_t nint, nbl, nchan, npol;
+  int32_t vis_dtype;
+  double tint_s;
+  const double *freq_ghz;
+  const double *uvw_m;
+  const double *dm;
+  int32_t ndm;
+  const int32_t *width;
+  int32_t nwidth;
+  int32_t npix;
+  double du, dv;
+  double kdm;
+  float threshold;
+  int32_t t_begin, t_end;
+} rf_plan_desc;
+
+typedef struct rf_plan rf_plan;
+
+typedef struct rf_plan_info {
+  int64_t n_images;     /* ndm * sum_w floor(nint / w)                         */
+  int32_t n_valid;      /* W: (baseline, channel) pairs inside the grid        */
+  int32_t n_dropped;    /* nbl * nchan - W                                     */
+  int32_t n_cells;      /* distinct occupied uv cells                          */
+  int32_t n_rows;       /* grid rows v or -v of which holds an occupied cell   */
+  int32_t max_delay;    /* largest delay in the table, integrations            */
+  int32_t npix;
+  size_t table_bytes;   /* bytes of the device table buffer actually used      */
+} rf_plan_info;
+
+/* One image's identity: DM trial index, width index, start integration. */
+typedef struct rf_image_tag { int32_t dm_idx, width_idx, t_int; } rf_image_tag;
+
+/* Per-image statistics (section 3.1 thresholding): signed peak at pixel
+ * (x, y), sigma = 1.4826 * lower median of |image|, snr = peak / sigma (0
+ * when sigma is 0). */
+typedef struct rf_image_stats { float peak, sigma, snr; int32_t x, y; } rf_image_stats;
+
+/* A candidate (section 3.3 candidate database record), 32 bytes. */
+typedef struct rf_candidate {
+  int32_t dm_idx, width_idx, t_int, x, y;
+  float snr, peak, sigma;
+} rf_candidate;
+
+/* Human-readable name of a status code (static storage). */
+const char *rf_status_string(rf_status s);
+
+/*
+ * rf_plan_table_bytes: size of the device buffer rf_plan_create needs for
+ * `desc` (an upper bound that depends on the shapes only).  Validates desc.
+ */
+rf_status rf_plan_table_bytes(const rf_plan_desc *desc, size_t *bytes);
+
+/*
+ * rf_plan_create: validate `desc`, compute the plan tables and return a plan.
+ * The integer delay table (section 2.1 footnote, delay relative to the top
+ * channel, rounded half-even to whole integrations) and the nearest uv cell
+ * of every (baseline, channel) are computed on the device in float64 with no
+ * fused multiply-add.  The cell-sorted gather order and the occupied-row list
+ * are derived on the host and uploaded.  d_tables must hold at least
+ * rf_plan_table_bytes bytes and must outlive the plan.  Synchronises
+ * `stream`.  On error *out is NULL and nothing is left allocated.
+ */
+rf_status rf_plan_create(const rf_plan_desc *desc, void *d_tables, size_t bytes,
+                         void *stream, rf_plan **out);
+
+/* rf_plan_destroy: free the host-side plan object (NULL is allowed). */
+rf_status rf_plan_destroy(rf_plan *plan);
+
+rf_status rf_plan_query(const rf_plan *plan, rf_plan_info *info);
+
+/* Copy the delay table, int32 [ndm][nchan], to host memory (synchronous). */
+rf_status rf_get_delays(const rf_plan *plan, int32_t *h_out);
+
+/* Copy the cell table, int32 [nbl][nchan][2] = (iu, iv), to host memory. */
+rf_status rf_get_cells(const rf_plan *plan, int32_t *h_out);
+
+/* Workspace bytes for `op` on `nimg` images (RF_OP_IMAGE, RF_OP_SEARCH) or
+ * for a whole segment (RF_OP_SEGMENT; nimg ignored). */
+rf_status rf_workspace_bytes(const rf_plan *plan, int32_t op, int64_t nimg, size_t *bytes);
+
+/*
+ * rf_dedisperse (section 2.2: dedispersion in the visibility domain):
+ *   d_out[t][b][c][p] = d_vis[t + d[dm_idx][c]][b][c][p]  if t + d < nint,
+ *                       0                                  otherwise.
+ * Both buffers are [nint][nbl][nchan][npol] of the plan's vis_dtype and must
+ * not overlap.  A pure copy: bit-exact in either storage type.
+ */
+rf_status rf_dedisperse(const rf_plan *plan, int32_t dm_idx, const void *d_vis,
+                        void *d_out, void *stream);
+
+/*
+ * rf_resample (Figure 2 loop over sampling time): decimating boxcar mean
+ *   d_out[k] = (sum_{j<width} d_in[k*width + j]) / width,  k < nin / width,
+ * accumulated in float32 in increasing j.  d_in is [nin][nbl][nchan][npol]
+ * of the plan's vis_dtype; d_out is RF_CF32 [nin / width][nbl][nchan][npol].
+ */
+rf_status rf_resample(const rf_plan *plan, int32_t width, const void *d_in, int32_t nin,
+                      void *d_out, void *stream);
+
+/*
+ * rf_grid: Stokes I (mean of the two polarisations, section 3.1) gridded to
+ * the nearest uv cell with unit weights:
+ *   G[n][iv mod N][iu mod N] = sum over valid (b, c) in that cell of V_I,
+ * summed in float32 in increasing b*nchan + c.  d_vis is RF_CF32
+ * [nimg][nbl][nchan][npol]; d_grid is RF_CF32 [nimg][N][N] (fully written).
+ */
+rf_status rf_grid(const rf_plan *plan, const void *d_vis, int32_t nimg, void *d_grid,
+                  void *stream);
+
+/*
+ * rf_image (section 3.2: 2-D FFT imaging):
+ *   img[n][Y][X] = (1/W) Re sum_{iu,iv} G[n][iv][iu]
+ *                  exp(+2 pi i (iu (X - N/2) + iv (Y - N/2)) / N),
+ * float32 [nimg][N][N], phase centre at pixel (N/2, N/2).  Images are
+ * transformed two at a time as the real and imaginary parts of one complex
+ * FFT of their Hermitian-symmetrised grids.  d_ws: rf_workspace_bytes(
+ * RF_OP_IMAGE, nimg) bytes.
+ */
+rf_status rf_image(const rf_plan *plan, const void *d_grid, int32_t nimg, float *d_img,
+                   void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * rf_search (section 3.1: threshold each image on S/N):
+ * per image, peak = signed max (ties: lowest y*N + x), sigma = 1.4826 *
+ * lower median of |img| (exact order statistic of rank floor((N*N-1)/2)),
+ * snr = peak / sigma.  If snr > threshold and t_begin <= tag.t_int < t_end a
+ * candidate is appended: slot = atomic increment of *d_ncand, written if
+ * slot < cap.  *d_ncand ends as the true count; the caller zeroes it before
+ * the first call and compares it with cap.  Candidate order is unspecified.
+ * d_tags[nimg] (device) names each image; d_stats[nimg] may be NULL.
+ */
+rf_status rf_search(const rf_plan *plan, const float *d_img, int32_t nimg,
+                    const rf_image_tag *d_tags, rf_image_stats *d_stats,
+                    rf_candidate *d_cand, int32_t cap, int32_t *d_ncand,
+                    void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * rf_search_segment: the whole search of one segment (every DM trial, every
+ * width, every integration), with the same results as the chain
+ * rf_dedisperse -> rf_resample -> rf_grid -> rf_image -> rf_search.
+ * d_vis: [nint][nbl][nchan][npol] of the plan's vis_dtype.  *d_ncand is set
+ * to 0 on the device first.  d_stats (nullable) receives [n_images] stats in
+ * (dm_idx, width_idx, k) order.  d_ws: rf_workspace_bytes(RF_OP_SEGMENT).
+ */
+rf_status rf_search_segment(const rf_plan *plan, const void *d_vis, rf_candidate *d_cand,
+                            int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,
+                            void *d_ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RF_H */

@@ -255,3 +255,25 @@ def is_marginal(img, snr, threshold, tol):
     if top == 0.0:
         return True
     return (top - second) / abs(top) < 10 * tol
+
+
+def dedisperse_window(vis, delay_row, t0, t1):
+    """Rows [t0, t1) of dedisperse(vis, delay_row), without forming the rest
+    (for sampling single images of a large segment).  float16 [..., 2]
+    storage is widened exactly, slice by slice."""
+    T = vis.shape[0]
+    shape = (t1 - t0,) + tuple(vis.shape[1:4])
+    out = np.zeros(shape, dtype=np.complex128)
+    for c, d in enumerate(np.asarray(delay_row)):
+        for t in range(t0, t1):
+            s = t + int(d)
+            if s < T:
+                out[t - t0, :, c, :] = as_complex(vis[s, :, c])
+    return out
+
+
+def image_at(vis, plan, i, j, k):
+    """The image of DM trial i, width index j, resampled integration k."""
+    w = plan.widths[j]
+    dd = dedisperse_window(vis, plan.delays[i], k * w, k * w + w)
+    return make_image(resample(dd, w)[0], plan)

@@ -1,0 +1,241 @@
+"""realfast search hot path on MI355X: Python binding of librf.
+
+Argument marshalling only: every step runs in librf's HIP kernels.  torch
+supplies device memory and the current stream.  The binding's names follow
+the C ABI (include/rf.h):
+
+    plan = Plan(freq_ghz, uvw_m, tint_s, dms, widths, npix, du, dv, nint=..., npol=2)
+    plan.dedisperse(vis, dm_idx)      # rf_dedisperse
+    plan.resample(x, width)           # rf_resample
+    plan.grid(vis)                    # rf_grid
+    plan.image(grid)                  # rf_image
+    plan.search(img, tags)            # rf_search
+    plan.search_segment(vis)          # rf_search_segment
+
+Visibilities are torch tensors on the GPU: complex64 [nint, nbl, nchan, npol]
+for RF_CF32 storage, or float16 [nint, nbl, nchan, npol, 2] for RF_CF16.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (RF_CF16, RF_CF32, RF_OP_IMAGE, RF_OP_SEARCH, RF_OP_SEGMENT,  # noqa: F401
+                   Candidate, ImageStats, ImageTag, RFError)
+
+__all__ = ["Plan", "RFError", "RF_CF32", "RF_CF16", "load_library", "CAND_DTYPE", "STATS_DTYPE"]
+
+CAND_DTYPE = np.dtype([("dm_idx", "<i4"), ("width_idx", "<i4"), ("t_int", "<i4"), ("x", "<i4"),
+                       ("y", "<i4"), ("snr", "<f4"), ("peak", "<f4"), ("sigma", "<f4")])
+STATS_DTYPE = np.dtype([("peak", "<f4"), ("sigma", "<f4"), ("snr", "<f4"), ("x", "<i4"),
+                        ("y", "<i4")])
+TAG_DTYPE = np.dtype([("dm_idx", "<i4"), ("width_idx", "<i4"), ("t_int", "<i4")])
+
+
+def load_library():
+    return _lib.load()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Plan:
+    """An immutable search plan (rf_plan) with its device tables."""
+
+    def __init__(self, freq_ghz, uvw_m, tint_s, dms, widths, npix, du, dv, nint, npol=2,
+                 vis_dtype=RF_CF32, kdm=4.15e-3, threshold=6.0, t_begin=0, t_end=None,
+                 device="cuda"):
+        torch = _torch()
+        lib = _lib.load()
+        self._freq = np.ascontiguousarray(freq_ghz, dtype=np.float64)
+        self._uvw = np.ascontiguousarray(uvw_m, dtype=np.float64).reshape(-1, 3)
+        self._dm = np.ascontiguousarray(dms, dtype=np.float64)
+        self._width = np.ascontiguousarray(widths, dtype=np.int32)
+        self.nint, self.nbl, self.nchan, self.npol = int(nint), self._uvw.shape[0], self._freq.size, int(npol)
+        self.vis_dtype = int(vis_dtype)
+        self.npix = int(npix)
+        self.widths = [int(w) for w in self._width]
+        self.ndm = self._dm.size
+        d = _lib.PlanDesc()
+        d.nint, d.nbl, d.nchan, d.npol = self.nint, self.nbl, self.nchan, self.npol
+        d.vis_dtype = self.vis_dtype
+        d.tint_s = float(tint_s)
+        d.freq_ghz = self._freq.ctypes.data_as(_lib.c_dp)
+        d.uvw_m = self._uvw.ctypes.data_as(_lib.c_dp)
+        d.dm = self._dm.ctypes.data_as(_lib.c_dp)
+        d.ndm = self._dm.size
+        d.width = self._width.ctypes.data_as(_lib.c_ip)
+        d.nwidth = self._width.size
+        d.npix = self.npix
+        d.du, d.dv, d.kdm = float(du), float(dv), float(kdm)
+        d.threshold = float(threshold)
+        d.t_begin = int(t_begin)
+        d.t_end = self.nint if t_end is None else int(t_end)
+        self._desc = d
+        nbytes = _lib.c_size(0)
+        _lib.check(lib.rf_plan_table_bytes(ctypes.byref(d), ctypes.byref(nbytes)), "rf_plan_table_bytes")
+        self.device = torch.device(device)
+        self.tables = torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _lib.check(lib.rf_plan_create(ctypes.byref(d), _ptr(self.tables), nbytes.value, _stream(),
+                                      ctypes.byref(h)), "rf_plan_create")
+        self._h = h
+        info = _lib.PlanInfo()
+        _lib.check(lib.rf_plan_query(h, ctypes.byref(info)), "rf_plan_query")
+        self.info = {k: getattr(info, k) for k, _ in _lib.PlanInfo._fields_}
+        self.n_images = int(info.n_images)
+        self.W = int(info.n_valid)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().rf_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # ---------------------------------------------------------------- helpers
+    @property
+    def handle(self):
+        return self._h
+
+    def image_base(self, dm_idx, width_idx):
+        per_dm = sum(self.nint // w for w in self.widths)
+        return dm_idx * per_dm + sum(self.nint // w for w in self.widths[:width_idx])
+
+    def delays(self):
+        out = np.empty((self.ndm, self.nchan), dtype=np.int32)
+        _lib.check(_lib.load().rf_get_delays(self._h, out.ctypes.data_as(ctypes.c_void_p)), "rf_get_delays")
+        return out
+
+    def cells(self):
+        out = np.empty((self.nbl, self.nchan, 2), dtype=np.int32)
+        _lib.check(_lib.load().rf_get_cells(self._h, out.ctypes.data_as(ctypes.c_void_p)), "rf_get_cells")
+        return out
+
+    def workspace_bytes(self, op, nimg=0):
+        n = _lib.c_size(0)
+        _lib.check(_lib.load().rf_workspace_bytes(self._h, op, nimg, ctypes.byref(n)), "rf_workspace_bytes")
+        return n.value
+
+    def workspace(self, op, nimg=0):
+        torch = _torch()
+        return torch.empty(max(1, self.workspace_bytes(op, nimg)), dtype=torch.uint8, device=self.device)
+
+    def _vis_shape(self, nint):
+        if self.vis_dtype == RF_CF32:
+            return (nint, self.nbl, self.nchan, self.npol)
+        return (nint, self.nbl, self.nchan, self.npol, 2)
+
+    def empty_vis(self, nint=None):
+        torch = _torch()
+        nint = self.nint if nint is None else nint
+        dt = torch.complex64 if self.vis_dtype == RF_CF32 else torch.float16
+        return torch.empty(self._vis_shape(nint), dtype=dt, device=self.device)
+
+    def _check_vis(self, t, nint, cf32_only=False, name="vis"):
+        torch = _torch()
+        want_dt = torch.complex64 if (cf32_only or self.vis_dtype == RF_CF32) else torch.float16
+        want_shape = (nint, self.nbl, self.nchan, self.npol) + (() if want_dt == torch.complex64 else (2,))
+        if t.dtype != want_dt or tuple(t.shape) != want_shape or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError(f"{name}: expected contiguous cuda {want_dt} {want_shape}, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+
+    # ---------------------------------------------------------------- steps
+    def dedisperse(self, vis, dm_idx, out=None, stream=None):
+        self._check_vis(vis, self.nint)
+        if out is None:
+            out = self.empty_vis()
+        self._check_vis(out, self.nint, name="out")
+        _lib.check(_lib.load().rf_dedisperse(self._h, int(dm_idx), _ptr(vis), _ptr(out), _stream(stream)),
+                   "rf_dedisperse")
+        return out
+
+    def resample(self, x, width, out=None, stream=None):
+        torch = _torch()
+        nin = x.shape[0]
+        self._check_vis(x, nin, name="x")
+        nout = nin // int(width)
+        if out is None:
+            out = torch.empty((nout, self.nbl, self.nchan, self.npol), dtype=torch.complex64, device=self.device)
+        self._check_vis(out, nout, cf32_only=True, name="out")
+        _lib.check(_lib.load().rf_resample(self._h, int(width), _ptr(x), nin, _ptr(out), _stream(stream)),
+                   "rf_resample")
+        return out
+
+    def grid(self, vis, out=None, stream=None):
+        torch = _torch()
+        nimg = vis.shape[0]
+        self._check_vis(vis, nimg, cf32_only=True)
+        if out is None:
+            out = torch.empty((nimg, self.npix, self.npix), dtype=torch.complex64, device=self.device)
+        if out.dtype != torch.complex64 or tuple(out.shape) != (nimg, self.npix, self.npix) or not out.is_contiguous():
+            raise ValueError("grid out: expected complex64 [nimg, N, N]")
+        _lib.check(_lib.load().rf_grid(self._h, _ptr(vis), nimg, _ptr(out), _stream(stream)), "rf_grid")
+        return out
+
+    def image(self, grid, out=None, ws=None, stream=None):
+        torch = _torch()
+        nimg = grid.shape[0]
+        if grid.dtype != torch.complex64 or tuple(grid.shape) != (nimg, self.npix, self.npix) or not grid.is_contiguous():
+            raise ValueError("grid: expected complex64 [nimg, N, N]")
+        if out is None:
+            out = torch.empty((nimg, self.npix, self.npix), dtype=torch.float32, device=self.device)
+        if ws is None:
+            ws = self.workspace(RF_OP_IMAGE, nimg)
+        _lib.check(_lib.load().rf_image(self._h, _ptr(grid), nimg, _ptr(out), _ptr(ws), ws.numel(),
+                                        _stream(stream)), "rf_image")
+        return out
+
+    def search(self, img, tags, cap=4096, ncand=None, cand=None, with_stats=True, stream=None):
+        """Threshold images; tags: int32 [nimg, 3] (dm_idx, width_idx, t_int).
+        Returns (candidates sorted by (dm_idx, width_idx, t_int), true count,
+        stats structured array or None).  Synchronises the stream."""
+        torch = _torch()
+        nimg = img.shape[0]
+        tags_t = torch.as_tensor(np.ascontiguousarray(tags, dtype=np.int32).reshape(nimg, 3), device=self.device)
+        stats = torch.empty((nimg, 5), dtype=torch.int32, device=self.device) if with_stats else None
+        if cand is None:
+            cand = torch.empty((max(cap, 1), 8), dtype=torch.int32, device=self.device)
+        if ncand is None:
+            ncand = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _lib.check(_lib.load().rf_search(self._h, _ptr(img), nimg, _ptr(tags_t), _ptr(stats), _ptr(cand),
+                                         int(cap), _ptr(ncand), None, 0, _stream(stream)), "rf_search")
+        return self._collect(cand, ncand, stats, cap)
+
+    def search_segment(self, vis, cap=65536, with_stats=False, ws=None, stream=None, collect=True):
+        torch = _torch()
+        self._check_vis(vis, self.nint)
+        if ws is None:
+            ws = self.workspace(RF_OP_SEGMENT)
+        cand = torch.empty((max(cap, 1), 8), dtype=torch.int32, device=self.device)
+        ncand = torch.zeros(1, dtype=torch.int32, device=self.device)
+        stats = torch.empty((self.n_images, 5), dtype=torch.int32, device=self.device) if with_stats else None
+        _lib.check(_lib.load().rf_search_segment(self._h, _ptr(vis), _ptr(cand), int(cap), _ptr(ncand),
+                                                 _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)),
+                   "rf_search_segment")
+        if not collect:
+            return cand, ncand, stats
+        return self._collect(cand, ncand, stats, cap)
+
+    @staticmethod
+    def _collect(cand, ncand, stats, cap):
+        n = int(ncand.item())
+        rows = cand[: min(n, cap)].cpu().numpy().view(CAND_DTYPE).reshape(-1)
+        rows = np.sort(rows, order=["dm_idx", "width_idx", "t_int"])
+        st = stats.cpu().numpy().view(STATS_DTYPE).reshape(-1) if stats is not None else None
+        return rows, n, st

@@ -1,0 +1,169 @@
+// Workgroup-cooperative inverse FFTs in LDS (Stockham autosort, radix 4/8/16).
+//
+// A workgroup transforms F independent length-N sequences held in LDS, each
+// starting STRIDE complex elements after the previous one.  A pass of radix R
+// (with NS = product of the earlier radices) performs, for every butterfly j
+// in [0, N/R):
+//   v[r] = x[j + r N/R] * w^(r (j mod NS)),  w = exp(+2 pi i / (NS R))
+//   v    = DFT_R(v)            (inverse sign, natural order)
+//   y[(j / NS) NS R + (j mod NS) + r NS] = v[r]
+// which is the classical self-sorting Stockham formulation of the radix-R
+// Cooley-Tukey FFT: after the last pass y is the inverse DFT in natural
+// order.  Each thread loads all of its butterflies' inputs into registers
+// before a barrier and writes them after it, so one LDS buffer suffices.
+// Twiddles come from an LDS table tw[m] = exp(+2 pi i m / N) computed on the
+// host in float64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace rf {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 crot(float2 x, float c, float s) {
+  return make_float2(x.x * c - x.y * s, x.x * s + x.y * c);
+}
+
+// x * exp(+2 pi i e / 16).  e is a compile-time constant at every call site
+// after unrolling, so the switch folds away and trivial rotations cost nothing.
+__device__ __forceinline__ float2 rot16(float2 x, int e) {
+  constexpr float c1 = 0.92387953251128675613f;  // cos(pi/8)
+  constexpr float s1 = 0.38268343236508977173f;  // sin(pi/8)
+  constexpr float h = 0.70710678118654752440f;   // cos(pi/4)
+  switch (e & 15) {
+    case 0: return x;
+    case 1: return crot(x, c1, s1);
+    case 2: return make_float2(h * (x.x - x.y), h * (x.x + x.y));
+    case 3: return crot(x, s1, c1);
+    case 4: return make_float2(-x.y, x.x);
+    case 5: return crot(x, -s1, c1);
+    case 6: return make_float2(-h * (x.x + x.y), h * (x.x - x.y));
+    case 7: return crot(x, -c1, s1);
+    case 8: return make_float2(-x.x, -x.y);
+    case 9: return crot(x, -c1, -s1);
+    case 10: return make_float2(h * (x.y - x.x), -h * (x.x + x.y));
+    case 11: return crot(x, -s1, -c1);
+    case 12: return make_float2(x.y, -x.x);
+    case 13: return crot(x, s1, -c1);
+    case 14: return make_float2(h * (x.x + x.y), h * (x.y - x.x));
+    default: return crot(x, c1, -s1);
+  }
+}
+
+template <int R>
+__device__ constexpr int bitrev(int i) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// In-register inverse DFT of length R in {2, 4, 8, 16}: bit-reversed
+// radix-2 decimation in time, natural-order output.
+template <int R>
+__device__ __forceinline__ void dft(float2 (&v)[R]) {
+  float2 t[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) t[i] = v[bitrev<R>(i)];
+#pragma unroll
+  for (int len = 2; len <= R; len *= 2) {
+#pragma unroll
+    for (int i = 0; i < R; i += len) {
+#pragma unroll
+      for (int k = 0; k < len / 2; ++k) {
+        const float2 a = t[i + k];
+        const float2 b = rot16(t[i + k + len / 2], k * (16 / len));
+        t[i + k] = cadd(a, b);
+        t[i + k + len / 2] = csub(a, b);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = t[i];
+}
+
+template <int N, int R, int NS, int F, int NT, int STRIDE>
+__device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *tw, int tid) {
+  constexpr int NB = N / R;
+  constexpr int TOT = F * NB;
+  constexpr int Q = (TOT + NT - 1) / NT;
+  float2 v[Q][R];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = tid + q * NT;
+    if ((TOT % NT) == 0 || idx < TOT) {
+      const int f = idx / NB, j = idx % NB;
+      const float2 *src = buf + f * STRIDE + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[r * NB];
+      if (NS > 1) {
+        const int jm = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[jm * r * (N / (NS * R))]);
+      }
+      dft<R>(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = tid + q * NT;
+    if ((TOT % NT) == 0 || idx < TOT) {
+      const int f = idx / NB, j = idx % NB;
+      float2 *dst = buf + f * STRIDE + (j / NS) * NS * R + (j % NS);
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * NS] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Inverse (exp(+i)) unnormalised FFT of F sequences of length N in LDS.
+// Callers synchronise before (inputs written) and may read after return.
+template <int N, int F, int NT, int STRIDE>
+__device__ __forceinline__ void fft_inverse(float2 *buf, const float2 *tw, int tid) {
+  static_assert(N >= 64 && N <= 2048 && (N & (N - 1)) == 0, "N must be 2^k in [64, 2048]");
+  if constexpr (N == 64) {
+    stockham_pass<N, 16, 1, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 4, 16, F, NT, STRIDE>(buf, tw, tid);
+  } else if constexpr (N == 128) {
+    stockham_pass<N, 16, 1, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 8, 16, F, NT, STRIDE>(buf, tw, tid);
+  } else if constexpr (N == 256) {
+    stockham_pass<N, 16, 1, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 16, 16, F, NT, STRIDE>(buf, tw, tid);
+  } else if constexpr (N == 512) {
+    stockham_pass<N, 8, 1, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 8, 8, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 8, 64, F, NT, STRIDE>(buf, tw, tid);
+  } else if constexpr (N == 1024) {
+    stockham_pass<N, 16, 1, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 16, 16, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 4, 256, F, NT, STRIDE>(buf, tw, tid);
+  } else {
+    stockham_pass<N, 16, 1, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 16, 16, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 8, 256, F, NT, STRIDE>(buf, tw, tid);
+  }
+}
+
+// Launch shapes of the two imaging passes for image side N.
+template <int N>
+struct RowCfg {
+  static constexpr int NT = 512;
+  static constexpr int F = (8192 / N) < 64 ? (8192 / N) : 64;  // rows per workgroup
+};
+template <int N>
+struct ColCfg {
+  static constexpr int NT = 1024;
+  static constexpr int COLS = (16384 / N) < N ? (16384 / N) : N;  // columns per workgroup
+  static constexpr int STRIDE = N + 1;                            // padded column stride
+};
+
+}  // namespace rf

@@ -1,0 +1,132 @@
+// 2-D FFT imaging (Law et al. 2018, section 3.2: "the 2d FFT for imaging").
+//
+//   img[Y][X] = (1/W) Re sum_{iu,iv} G[iv][iu] exp(+2 pi i (iu (X - N/2) + iv (Y - N/2)) / N)
+//
+// Two images a, b share one complex transform.  The real part of an inverse
+// DFT equals the inverse DFT of the Hermitian part H[k] = (G[k] + conj G[-k])/2,
+// so Z = H_a + i H_b transforms to W (img_a + i img_b).  The shift of the
+// phase centre to pixel (N/2, N/2) is the factor (-1)^(iu + iv) on the grid.
+// Pass 1 (rows): for each occupied row v of the symmetrised grid, build Z[v][:]
+// from rows v and -v of both grids in LDS and transform along u.  Rows with no
+// samples are skipped and never stored.  Pass 2 (columns): gather a tile of
+// columns of the row-transformed data (zero for skipped rows), transform along
+// v and write Re / W and Im / W to the two images.
+#include "rf_internal.h"
+#include "fft.h"
+
+namespace {
+
+using namespace rf;
+
+template <int N>
+__global__ __launch_bounds__(RowCfg<N>::NT) void k_rows_dense(
+    const float2 *__restrict__ grid, int nimg, const int32_t *__restrict__ rows, int n_rows,
+    int row_blocks, const float2 *__restrict__ tw_g, float2 *__restrict__ M) {
+  constexpr int F = RowCfg<N>::F, NT = RowCfg<N>::NT;
+  __shared__ float2 buf[F * N];
+  __shared__ float2 tw[N];
+  const int pair = blockIdx.x / row_blocks;
+  const int slot0 = (blockIdx.x % row_blocks) * F;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
+  const size_t npix2 = (size_t)N * N;
+  const float2 *Ga = grid + (size_t)(2 * pair) * npix2;
+  const float2 *Gb = Ga + npix2;
+  const bool hasb = 2 * pair + 1 < nimg;
+  for (int e = tid; e < F * N; e += NT) {
+    const int f = e / N, u = e % N;
+    const int slot = slot0 + f;
+    float2 z = make_float2(0.f, 0.f);
+    if (slot < n_rows) {
+      const int r = rows[slot];
+      const int rm = (N - r) & (N - 1);
+      const int um = (N - u) & (N - 1);
+      const float2 a = Ga[(size_t)r * N + u], am = Ga[(size_t)rm * N + um];
+      float2 b = make_float2(0.f, 0.f), bm = b;
+      if (hasb) {
+        b = Gb[(size_t)r * N + u];
+        bm = Gb[(size_t)rm * N + um];
+      }
+      const float px = a.x + am.x, py = a.y - am.y;   // G_a[k] + conj G_a[-k]
+      const float qx = b.x + bm.x, qy = b.y - bm.y;   // G_b[k] + conj G_b[-k]
+      const float sg = ((r + u) & 1) ? -0.5f : 0.5f;  // (-1)^(u+v) / 2
+      z = make_float2(sg * (px - qy), sg * (py + qx));
+    }
+    buf[f * N + u] = z;
+  }
+  __syncthreads();
+  fft_inverse<N, F, NT, N>(buf, tw, tid);
+  for (int e = tid; e < F * N; e += NT) {
+    const int f = e / N, x = e % N;
+    const int slot = slot0 + f;
+    if (slot < n_rows) M[((size_t)pair * n_rows + slot) * N + x] = buf[f * N + x];
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_image(
+    const float2 *__restrict__ M, int n_rows, const int32_t *__restrict__ row_slot, int nimg,
+    float inv_w, const float2 *__restrict__ tw_g, float *__restrict__ img) {
+  constexpr int COLS = ColCfg<N>::COLS, NT = ColCfg<N>::NT, S = ColCfg<N>::STRIDE;
+  constexpr int CB = N / COLS;
+  __shared__ float2 buf[COLS * S];
+  __shared__ float2 tw[N];
+  const int pair = blockIdx.x / CB;
+  const int x0 = (blockIdx.x % CB) * COLS;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
+  const float2 *Mp = M + (size_t)pair * n_rows * N + x0;
+  for (int e = tid; e < N * COLS; e += NT) {
+    const int r = e / COLS, x = e % COLS;
+    const int slot = row_slot[r];
+    buf[x * S + r] = slot >= 0 ? Mp[(size_t)slot * N + x] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_inverse<N, COLS, NT, S>(buf, tw, tid);
+  float *ia = img + (size_t)(2 * pair) * N * N + x0;
+  float *ib = ia + (size_t)N * N;
+  const bool hasb = 2 * pair + 1 < nimg;
+  for (int e = tid; e < N * COLS; e += NT) {
+    const int y = e / COLS, x = e % COLS;
+    const float2 v = buf[x * S + y];
+    ia[(size_t)y * N + x] = v.x * inv_w;
+    if (hasb) ib[(size_t)y * N + x] = v.y * inv_w;
+  }
+}
+
+template <int N>
+rf_status image_dense_n(const rf_plan *p, const float2 *grid, int nimg, float *img, float2 *ws,
+                        hipStream_t s) {
+  const int npairs = (nimg + 1) / 2;
+  if (npairs == 0) return RF_OK;
+  const float inv_w = p->W > 0 ? 1.0f / (float)p->W : 0.0f;
+  if (p->n_rows == 0 || p->W == 0) return launch_zero_f32(img, (size_t)nimg * N * N, s);
+  const int rb = (p->n_rows + RowCfg<N>::F - 1) / RowCfg<N>::F;
+  k_rows_dense<N><<<(unsigned)((size_t)rb * npairs), RowCfg<N>::NT, 0, s>>>(
+      grid, nimg, p->d_rows, p->n_rows, rb, p->d_tw, ws);
+  RF_HIP_TRY(hipGetLastError());
+  constexpr int CB = N / ColCfg<N>::COLS;
+  k_cols_image<N><<<(unsigned)((size_t)CB * npairs), ColCfg<N>::NT, 0, s>>>(
+      ws, p->n_rows, p->d_row_slot, nimg, inv_w, p->d_tw, img);
+  RF_HIP_TRY(hipGetLastError());
+  return RF_OK;
+}
+
+}  // namespace
+
+size_t image_ws_bytes(const rf_plan *p, int64_t nimg) {
+  return (size_t)((nimg + 1) / 2) * (size_t)p->n_rows * (size_t)p->npix * sizeof(float2);
+}
+
+rf_status launch_image_dense(const rf_plan *p, const float2 *grid, int nimg, float *img,
+                             float2 *ws, hipStream_t s) {
+  switch (p->npix) {
+    case 64: return image_dense_n<64>(p, grid, nimg, img, ws, s);
+    case 128: return image_dense_n<128>(p, grid, nimg, img, ws, s);
+    case 256: return image_dense_n<256>(p, grid, nimg, img, ws, s);
+    case 512: return image_dense_n<512>(p, grid, nimg, img, ws, s);
+    case 1024: return image_dense_n<1024>(p, grid, nimg, img, ws, s);
+    case 2048: return image_dense_n<2048>(p, grid, nimg, img, ws, s);
+    default: return RF_EUNSUPPORTED;
+  }
+}

@@ -1,0 +1,90 @@
+// Internal declarations shared by the C-ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/rf.h"
+
+// Host-side plan object.  Immutable after rf_plan_create.
+struct rf_plan {
+  // description (scalars and host copies of the arrays)
+  int32_t nint, nbl, nchan, npol, vis_dtype, ndm, nwidth, npix;
+  double tint_s, du, dv, kdm;
+  float threshold;
+  int32_t t_begin, t_end;
+  std::vector<double> freq, uvw, dm;
+  std::vector<int32_t> width;
+
+  // derived
+  int32_t W;          // valid (baseline, channel) pairs
+  int32_t n_dropped;
+  int32_t n_cells;    // distinct occupied cells
+  int32_t n_rows;     // occupied rows of the Hermitian-symmetrised grid
+  int32_t max_delay;
+  int64_t n_images;
+  size_t table_bytes;
+  std::vector<int64_t> img_base;  // [ndm * nwidth] first image index of (dm, width)
+
+  // device tables (inside the caller's table buffer)
+  int32_t *d_delay;         // [ndm][nchan]
+  int32_t *d_cells;         // [nbl][nchan][2] (iu, iv)
+  int32_t *d_contrib;       // [W] pair index b*nchan + c, sorted by (cell, pair)
+  int32_t *d_ucell;         // [n_cells] linear cell (iv mod N) * N + (iu mod N), ascending
+  int32_t *d_ucell_off;     // [n_cells + 1] CSR offsets into d_contrib
+  int32_t *d_rows;          // [n_rows] occupied rows, ascending
+  int32_t *d_row_slot;      // [N] compact slot of a row in d_rows, or -1
+  float2 *d_tw;             // [N] exp(+2 pi i m / N)
+
+  // host copies used by rf_get_* and the launchers
+  std::vector<int32_t> h_delay;
+  std::vector<int32_t> h_cells;
+};
+
+#define RF_HIP_TRY(expr)                      \
+  do {                                        \
+    hipError_t _e = (expr);                   \
+    if (_e != hipSuccess) return RF_EHIP;     \
+  } while (0)
+
+// ---- launchers (each returns RF_OK or RF_EHIP; arguments already validated)
+
+// plan tables (float64, no contraction)
+rf_status launch_plan_tables(const double *d_freq, const double *d_uvw, const double *d_dm,
+                             int nchan, int nbl, int ndm, double nu_ref, double tint_s,
+                             double kdm, double du, double dv, int32_t *d_delay,
+                             int32_t *d_cells, hipStream_t s);
+
+// dedispersion / resampling
+rf_status launch_dedisperse(const rf_plan *p, const int32_t *d_delay_row, const void *in,
+                            void *out, hipStream_t s);
+rf_status launch_resample(const rf_plan *p, int width, const void *in, int in_dtype, int nin,
+                          float2 *out, hipStream_t s);
+
+// dense gridding: vis CF32 [nimg][nbl][nchan][npol] -> grid [nimg][N][N]
+rf_status launch_grid_dense(const rf_plan *p, const float2 *vis, int nimg, float2 *grid,
+                            hipStream_t s);
+
+// imaging from dense grids; ws holds [ceil(nimg/2)][n_rows][N] float2
+size_t image_ws_bytes(const rf_plan *p, int64_t nimg);
+rf_status launch_image_dense(const rf_plan *p, const float2 *grid, int nimg, float *img,
+                             float2 *ws, hipStream_t s);
+
+// statistics, threshold and candidates
+struct rf_tag_gen {       // implicit tags: image n -> (dm_idx, width_idx, (k0 + n) * w)
+  int32_t dm_idx, width_idx, width, k0;
+};
+rf_status launch_search(const rf_plan *p, const float *img, int nimg, const rf_image_tag *tags,
+                        const rf_tag_gen *gen, rf_image_stats *stats, rf_candidate *cand,
+                        int cap, int32_t *ncand, hipStream_t s);
+rf_status launch_zero_i32(int32_t *p, int n, hipStream_t s);
+rf_status launch_zero_f32(float *p, size_t nfloat, hipStream_t s);
+
+// whole segment
+size_t segment_ws_bytes(const rf_plan *p);
+rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
+                      int32_t *ncand, rf_image_stats *stats, void *ws, size_t ws_bytes,
+                      hipStream_t s);

@@ -1,0 +1,200 @@
+"""HIP path against the CPU oracle, step by step and end to end.
+
+Bars: integer tables, dedispersed visibilities and candidate keys are
+bit-exact; float results agree to 1e-5 of the reference maximum (float32
+storage) or 3e-3 (float16 storage against the float64 oracle on the
+unrounded input).  Every call goes through librf's C ABI.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import rfgen
+from helpers import cand_keys, gpu_plan, oracle_plan, rel_err, upload
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL16 = 3e-3
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+PRESETS = {
+    "tiny": rfgen.tiny,
+    "small": rfgen.smallcase,
+    "small_n64_p1": lambda: rfgen.smallcase(nant=6, nint=9, nchan=20, npix=64, npol=1, seed=9),
+    "small_n512": lambda: rfgen.smallcase(nant=12, nint=7, nchan=33, npix=512, seed=8),
+}
+
+
+@pytest.mark.parametrize("name", ["tiny", "small", "small_n64_p1", "small_n512", "survey"])
+def test_plan_tables_bit_exact(torch, name):
+    p = rfgen.survey() if name == "survey" else PRESETS[name]()
+    say("tables", name)
+    g = gpu_plan(p)
+    o = oracle_plan(p)
+    assert np.array_equal(g.delays(), o.delays)
+    cells = g.cells()
+    assert np.array_equal(cells[..., 0], o.iu)
+    assert np.array_equal(cells[..., 1], o.iv)
+    assert g.W == o.W
+    assert g.info["max_delay"] == int(o.delays.max())
+
+
+@pytest.mark.parametrize("name", ["tiny", "small", "small_n64_p1"])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_dedisperse_bit_exact(torch, name, dtype):
+    p = PRESETS[name]()
+    say("dedisperse", name, dtype)
+    vis = p.make_vis()
+    g = gpu_plan(p, vis_dtype=dtype)
+    o = oracle_plan(p)
+    dv = upload(vis, dtype)
+    host = dv.cpu().numpy()
+    for i in range(len(p.dms)):
+        out = g.dedisperse(dv, i).cpu().numpy()
+        ref = oracle.dedisperse(oracle.as_complex(host), o.delays[i])
+        if dtype == 0:
+            assert np.array_equal(out.astype(np.complex128), ref), i
+        else:
+            assert np.array_equal(oracle.as_complex(out), ref), i
+
+
+@pytest.mark.parametrize("name", ["tiny", "small", "small_n64_p1"])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_resample(torch, name, dtype):
+    p = PRESETS[name]()
+    say("resample", name, dtype)
+    vis = p.make_vis()
+    g = gpu_plan(p, vis_dtype=dtype)
+    dv = upload(vis, dtype)
+    ref_in = oracle.as_complex(dv.cpu().numpy())
+    for w in (1, 2, 3, 4, 8, p.nint):
+        out = g.resample(dv, w).cpu().numpy()
+        ref = oracle.resample(ref_in, w)
+        assert out.shape == ref.shape
+        assert rel_err(out.real, ref.real) < 1e-6 and rel_err(out.imag, ref.imag) < 1e-6, w
+
+
+@pytest.mark.parametrize("name", ["tiny", "small", "small_n64_p1", "small_n512"])
+def test_grid_and_image(torch, name):
+    p = PRESETS[name]()
+    say("grid+image", name)
+    vis = p.make_vis()
+    g = gpu_plan(p)
+    o = oracle_plan(p)
+    nimg = min(p.nint, 5)   # odd count: the last image has no partner
+    dv = upload(vis[:nimg])
+    grid = g.grid(dv)
+    gh = grid.cpu().numpy()
+    img = g.image(grid).cpu().numpy()
+    for k in range(nimg):
+        G = oracle.grid(oracle.stokes_i(vis[k].astype(np.complex128)), o.iu, o.iv, o.valid, p.npix)
+        assert rel_err(gh[k].real, G.real) < TOL32 and rel_err(gh[k].imag, G.imag) < TOL32
+        ref = oracle.image(G, o.W)
+        e = rel_err(img[k], ref)
+        assert e < TOL32, (k, e)
+
+
+@pytest.mark.parametrize("name", ["tiny", "small"])
+def test_search_stats_exact_on_same_image(torch, name):
+    """Given the same float32 image, peak, argmax and the lower median are
+    exact order statistics and must match bit for bit."""
+    p = PRESETS[name]()
+    say("search stats", name)
+    g = gpu_plan(p)
+    vis = p.make_vis()
+    nimg = min(p.nint, 6)
+    img_t = g.image(g.grid(upload(vis[:nimg])))
+    # plant ties and a flat image
+    img_t[1].fill_(0.25)
+    img_t[2, 3, 5] = float(img_t[2].max()) + 1.0
+    img_t[2, 7, 1] = float(img_t[2, 3, 5])
+    img = img_t.cpu().numpy()
+    tags = np.array([[0, 0, k] for k in range(nimg)], np.int32)
+    rows, n, st = g.search(img_t, tags, cap=64)
+    for k in range(nimg):
+        flat = img[k].ravel()
+        idx = int(np.argmax(flat))
+        a = np.sort(np.abs(flat))
+        med = a[(a.size - 1) // 2]
+        assert st[k]["peak"] == flat[idx]
+        assert (st[k]["x"], st[k]["y"]) == (idx % p.npix, idx // p.npix)
+        assert st[k]["sigma"] == np.float32(1.4826) * med
+    assert (st[2]["x"], st[2]["y"]) == (5, 3), "ties go to the lowest flat index"
+
+
+def _segment_parity(p, dtype, tol):
+    o = oracle_plan(p)
+    g = gpu_plan(p, vis_dtype=dtype)
+    vis = p.make_vis()
+    dv = upload(vis, dtype)
+    rows, n, st = g.search_segment(dv, cap=4096, with_stats=True)
+    ostats, ocands, oimgs = oracle.search(vis, o, keep_images=True)
+    assert n == len(rows)
+    marginal = set()
+    for key, ref in ostats.items():
+        i, j, k = key
+        s = st[g.image_base(i, j) + k]
+        peak, x, y, sigma, snr = ref
+        if oracle.is_marginal(oimgs[key], snr, o.threshold, tol):
+            marginal.add(key)
+        else:
+            assert (int(s["x"]), int(s["y"])) == (x, y), key
+        # an order statistic moves by at most the largest pixel error, which
+        # the image bar bounds by tol * max|ref|
+        amax = float(np.max(np.abs(oimgs[key])))
+        assert abs(s["peak"] - peak) <= tol * amax, key
+        assert abs(s["sigma"] - sigma) <= 1.4826 * tol * amax, key
+    want = [c[:5] for c in ocands if (c[0], c[1], c[2] // p.widths[c[1]]) not in marginal]
+    got = [k for k in cand_keys(rows)
+           if (k[0], k[1], k[2] // p.widths[k[1]]) not in marginal]
+    assert got == want
+    return rows, marginal
+
+
+@pytest.mark.parametrize("dtype,tol", [(0, TOL32), (1, TOL16)])
+def test_segment_tiny(torch, dtype, tol):
+    p = rfgen.tiny()
+    say("segment tiny", dtype)
+    rows, marginal = _segment_parity(p, dtype, tol)
+    pulse = p.pulses[0]
+    assert cand_keys(rows) == [(pulse.dm_idx, pulse.width_idx, pulse.t0, pulse.x, pulse.y)]
+    say("marginal images excluded from the exact comparison:", len(marginal))
+    assert (pulse.dm_idx, pulse.width_idx, pulse.t0) not in marginal
+
+
+@pytest.mark.parametrize("dtype,tol", [(0, TOL32), (1, TOL16)])
+def test_segment_small(torch, dtype, tol):
+    p = rfgen.smallcase()
+    say("segment small", dtype)
+    rows, _ = _segment_parity(p, dtype, tol)
+    pulse = p.pulses[0]
+    assert (pulse.dm_idx, pulse.width_idx, pulse.t0, pulse.x, pulse.y) in cand_keys(rows)
+
+
+def test_segment_window_and_capacity(torch):
+    p = rfgen.tiny()
+    say("segment window/cap")
+    vis = upload(p.make_vis())
+    g = gpu_plan(p, t_begin=1)
+    rows, n, _ = g.search_segment(vis, cap=16)
+    assert n == 0
+    p2 = rfgen.tiny()
+    p2.threshold = 0.5   # every image is a candidate
+    g2 = gpu_plan(p2)
+    rows, n, _ = g2.search_segment(vis, cap=7)
+    assert n == p2.n_images() and len(rows) == 7
