@@ -91,9 +91,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--storage", choices=["cf32", "cf16"], default="cf32")
     ap.add_argument("--workload", choices=["survey", "tiny"], default="survey")
-    ap.add_argument("--cpu-images", type=int, default=96)
+    ap.add_argument("--cpu-images", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-kernel-leg", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain step-chain comparison")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -152,56 +152,67 @@ def main():
     wall = time.perf_counter() - t0
     step_s = wall / args.steps
     img_s = plan.n_images / step_s
-    seg_s = p.nint * p.tint_s
     keys = {(int(r["dm_idx"]), int(r["width_idx"]), int(r["t_int"]), int(r["x"]), int(r["y"])) for r in rows}
+    seg_s = p.nint * p.tint_s
     found = sum((q.dm_idx, q.width_idx, q.t0, q.x, q.y) in keys for q in p.pulses)
     log(f"{img_s:.0f} images/s, {step_s * 1e3:.1f} ms/step, RTF {seg_s / step_s:.2f}, "
         f"pulses recovered {found}/{len(p.pulses)}, candidates {n}")
 
-    kernels = {}
-    roof = None
-    if not args.no_kernel_leg:
-        N = p.npix
-        nb = 64
-        per_int = p.nbl * p.nchan * p.npol
-        dd = plan.empty_vis()
-        rs = torch.empty((p.nint, p.nbl, p.nchan, p.npol), dtype=torch.complex64, device=dev)
-        grid = torch.empty((nb, N, N), dtype=torch.complex64, device=dev)
-        img = torch.empty((nb, N, N), dtype=torch.float32, device=dev)
-        iws = plan.workspace(rf.RF_OP_IMAGE, nb)
-        tags = torch.zeros((nb, 3), dtype=torch.int32, device=dev)
-        cand = torch.empty((cap, 8), dtype=torch.int32, device=dev)
-        ncand = torch.zeros(1, dtype=torch.int32, device=dev)
-        L = rf.load_library()
-        h = plan.handle
-        sp = rf._stream(stream)
-        P = rf._ptr
-        plan.dedisperse(dvis, len(p.dms) - 1, out=dd)
-        plan.resample(dd, 1, out=rs)
-        plan.grid(rs[:nb], out=grid)
-        plan.image(grid, out=img, ws=iws)
-        reps = 20
-        kernels["rf_dedisperse"] = event_time(lambda: L.rf_dedisperse(h, len(p.dms) - 1, P(dvis), P(dd), sp), reps, stream)
-        kernels["rf_resample_w1"] = event_time(lambda: L.rf_resample(h, 1, P(dd), p.nint, P(rs), sp), reps, stream)
-        kernels["rf_grid_64"] = event_time(lambda: L.rf_grid(h, P(rs), nb, P(grid), sp), reps, stream)
-        kernels["rf_image_64"] = event_time(lambda: L.rf_image(h, P(grid), nb, P(img), P(iws), iws.numel(), sp), reps, stream)
-        kernels["rf_search_64"] = event_time(lambda: L.rf_search(h, P(img), nb, P(tags), None, P(cand), cap, P(ncand), None, 0, sp), reps, stream)
-        nw = len(p.widths)
-        calls = {"rf_dedisperse": len(p.dms), "rf_resample_w1": len(p.dms) * nw,
-                 "rf_grid_64": plan.n_images / nb, "rf_image_64": plan.n_images / nb,
-                 "rf_search_64": plan.n_images / nb}
-        share = {k: kernels[k] * calls[k] for k in kernels}
-        log("entry-point seconds per step (event-timed x calls): " +
-            ", ".join(f"{k}={v:.3f}" for k, v in share.items()))
-        # rf_search launches exactly one kernel (k_search); its algorithmic
-        # traffic is one read of each image: N^2 float32.
-        dur = kernels["rf_search_64"]
-        alg = nb * N * N * 4
-        ach = alg / dur / 1e9
-        roof = {"bound": "hbm", "kernel": "k_search", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_launch_us": round(dur * 1e6, 2), "alg_bytes_per_launch": alg}
-        kernels = {k: round(v * 1e6, 2) for k, v in kernels.items()}
+    # event-timed kernels of the fused path (one extra pass, not in the timed region)
+    N = p.npix
+    times, _, _ = plan.profile_segment(dvis, cap=cap, ws=ws)
+    nw = len(p.widths)
+    n_rows = plan.info["n_rows"]
+    pairs = len(p.dms) * sum((p.nint // w + 1) // 2 for w in p.widths)
+    log2n = int(np.log2(N))
+    in_bytes = dvis.numel() * dvis.element_size()
+    vi_bytes = sum(p.nint // w for w in p.widths) * p.nbl * p.nchan * 8
+    algo = {  # algorithmic work per step and its unit
+        "drs": (len(p.dms) * (in_bytes + vi_bytes), "B"),
+        "grid": (plan.n_images * (p.nbl * p.nchan + plan.info["n_cells"]) * 8, "B"),
+        "rows": (pairs * n_rows * 5 * N * log2n, "flop"),
+        "cols": (pairs * N * 5 * N * log2n, "flop"),
+    }
+    kernels = {k: {"ms_total": round(v[0], 2), "launches": v[1],
+                   "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None}
+               for k, v in times.items() if v[1]}
+    log("fused kernels (event-timed, one pass): " +
+        ", ".join(f"{k}={v['ms_total']:.1f} ms/{v['launches']}" for k, v in kernels.items()))
+    dom = max((k for k in algo if k in kernels), key=lambda k: kernels[k]["ms_total"])
+    total_units, unit = algo[dom]
+    launches = kernels[dom]["launches"]
+    avg_s = kernels[dom]["ms_total"] * 1e-3 / launches
+    per_launch = total_units / launches
+    if unit == "B":
+        ach = per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    else:
+        ach = per_launch / avg_s / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 2), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None}
+    roof.update({"avg_launch_us": round(avg_s * 1e6, 2), "alg_per_launch": per_launch,
+                 "launches": launches})
+    for k in algo:
+        if k in kernels:
+            u, un = algo[k]
+            rate = u / (kernels[k]["ms_total"] * 1e-3)
+            kernels[k]["achieved"] = (f"{rate / 1e9:.0f} GB/s" if un == "B" else f"{rate / 1e12:.2f} TFLOP/s")
+
+    plain = None
+    if not args.no_plain:
+        wsp = plan.workspace(rf.RF_OP_SEGMENT_STEPS)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rows_p, n_p, _ = plan.search_segment(dvis, cap=cap, ws=wsp, steps=True)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        keys_p = {(int(r["dm_idx"]), int(r["width_idx"]), int(r["t_int"]), int(r["x"]), int(r["y"])) for r in rows_p}
+        plain = {"path": "rf_search_segment_steps (plain fp32 step chain)", "ms_per_step": round(tp * 1e3, 1),
+                 "images_per_s": round(plan.n_images / tp, 1), "rtf": round(seg_s / tp, 3),
+                 "same_candidates": keys_p == keys}
+        log(f"plain step chain: {tp:.2f}s/step, {plan.n_images / tp:.0f} images/s, same candidates {keys_p == keys}")
+        del wsp
 
     out = {
         "metric": "images searched/sec",
@@ -220,11 +231,13 @@ def main():
                                f"{p.nchan} chans {p.f_lo_ghz}-{p.f_hi_ghz} GHz, {p.npol} pols "
                                f"{args.storage}, {len(p.dms)} DMs 0-{p.dms[-1]:g}, widths {p.widths}, "
                                f"{p.npix}^2 images",
-                   "images_per_step": plan.n_images, "path": "rf_search_segment"},
+                   "images_per_step": plan.n_images, "path": "rf_search_segment (fused)"},
         "rtf": round(seg_s / step_s, 3),
+        "plain_fp32_path": plain,
+        "speedup_vs_plain": round(plain["ms_per_step"] / (step_s * 1e3), 2) if plain else None,
         "pulses_recovered": f"{found}/{len(p.pulses)}",
         "candidates": n,
-        "kernel_us": kernels,
+        "kernels": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

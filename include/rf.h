@@ -16,8 +16,9 @@
  * come from rf_workspace_bytes.
  *
  * `stream` is a hipStream_t passed as void* (NULL is the null stream).  Every
- * call except rf_plan_create / rf_get_* enqueues its kernels on `stream` and
- * returns at once.  The returned status covers the host-side checks only; on
+ * call except rf_plan_create, rf_get_* and rf_search_segment (which each
+ * synchronise `stream` once, as documented there) enqueues its kernels on
+ * `stream` and returns at once.  The returned status covers the host-side checks only; on
  * any error nothing has been enqueued.  Faults found on the device are
  * reported as data (candidate overflow via the true count in *d_ncand).
  *
@@ -52,7 +53,7 @@ typedef int32_t rf_status;
 enum { RF_CF32 = 0, RF_CF16 = 1 };
 
 /* Workspace queries (rf_workspace_bytes `op`). */
-enum { RF_OP_IMAGE = 1, RF_OP_SEARCH = 2, RF_OP_SEGMENT = 3 };
+enum { RF_OP_IMAGE = 1, RF_OP_SEARCH = 2, RF_OP_SEGMENT = 3, RF_OP_SEGMENT_STEPS = 4 };
 
 /*
  * Plan description: the pipeline state of section 3.2 (observation metadata
@@ -153,7 +154,8 @@ rf_status rf_get_delays(const rf_plan *plan, int32_t *h_out);
 rf_status rf_get_cells(const rf_plan *plan, int32_t *h_out);
 
 /* Workspace bytes for `op` on `nimg` images (RF_OP_IMAGE, RF_OP_SEARCH) or
- * for a whole segment (RF_OP_SEGMENT; nimg ignored). */
+ * for a whole segment (RF_OP_SEGMENT for rf_search_segment,
+ * RF_OP_SEGMENT_STEPS for rf_search_segment_steps; nimg ignored). */
 rf_status rf_workspace_bytes(const rf_plan *plan, int32_t op, int64_t nimg, size_t *bytes);
 
 /*
@@ -214,15 +216,55 @@ rf_status rf_search(const rf_plan *plan, const float *d_img, int32_t nimg,
 
 /*
  * rf_search_segment: the whole search of one segment (every DM trial, every
- * width, every integration), with the same results as the chain
- * rf_dedisperse -> rf_resample -> rf_grid -> rf_image -> rf_search.
- * d_vis: [nint][nbl][nchan][npol] of the plan's vis_dtype.  *d_ncand is set
- * to 0 on the device first.  d_stats (nullable) receives [n_images] stats in
- * (dm_idx, width_idx, k) order.  d_ws: rf_workspace_bytes(RF_OP_SEGMENT).
+ * width, every integration; the loops of Figure 2), with the same results as
+ * the chain rf_dedisperse -> rf_resample -> rf_grid -> rf_image -> rf_search.
+ * Fused path: one pass over the segment per DM trial forms the resampled
+ * Stokes I samples of every width, the uv grid is never materialised (rows
+ * are gathered from cells) and no image is written to memory: the column
+ * transform reduces each image to its peak and to the pixels that can hold
+ * its lower median, bracketed around 0.6745 x its rms (known beforehand from
+ * Parseval's theorem).  An image whose median falls outside the bracket is
+ * recomputed exactly by the step chain, so sigma is always the exact lower
+ * median.  d_vis: [nint][nbl][nchan][npol] of the plan's vis_dtype.  *d_ncand
+ * is set to 0 on the device first.  d_stats (nullable) receives [n_images]
+ * stats in (dm_idx, width_idx, k) order.  d_ws: rf_workspace_bytes(
+ * RF_OP_SEGMENT).  Synchronises `stream` once before returning (to learn
+ * whether any image needs the exact recomputation).
  */
 rf_status rf_search_segment(const rf_plan *plan, const void *d_vis, rf_candidate *d_cand,
                             int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,
                             void *d_ws, size_t ws_bytes, void *stream);
+
+/* Device time of the fused path's kernels, per kernel kind, measured with
+ * HIP events on the launch stream (rf_search_segment_profile). */
+enum { RF_K_DRS = 0, RF_K_ROWS = 1, RF_K_COLS = 2, RF_K_SELECT = 3, RF_K_FALLBACK = 4,
+       RF_K_GRID = 5, RF_NK = 8 };
+typedef struct rf_kernel_times {
+  double ms[RF_NK];        /* summed event-timed duration, milliseconds */
+  int64_t launches[RF_NK]; /* number of launches timed                 */
+} rf_kernel_times;
+
+/*
+ * rf_search_segment_profile: rf_search_segment with an event pair recorded
+ * around every kernel launch; *times receives the summed durations per
+ * kernel kind.  Results are identical to rf_search_segment; the extra events
+ * and one synchronisation per DM trial make it slower, so time throughput
+ * with rf_search_segment.
+ */
+rf_status rf_search_segment_profile(const rf_plan *plan, const void *d_vis, rf_candidate *d_cand,
+                                    int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,
+                                    void *d_ws, size_t ws_bytes, void *stream,
+                                    rf_kernel_times *times);
+
+/*
+ * rf_search_segment_steps: the same search driven as the plain chain of the
+ * step entry points above (dense grids and images in the workspace), kept as
+ * the reference path that the fused one is measured against.  Asynchronous.
+ * d_ws: rf_workspace_bytes(RF_OP_SEGMENT_STEPS).
+ */
+rf_status rf_search_segment_steps(const rf_plan *plan, const void *d_vis, rf_candidate *d_cand,
+                                  int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,
+                                  void *d_ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -21,6 +21,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (RF_CF16, RF_CF32, RF_OP_IMAGE, RF_OP_SEARCH, RF_OP_SEGMENT,  # noqa: F401
+                   RF_OP_SEGMENT_STEPS,
                    Candidate, ImageStats, ImageTag, RFError)
 
 __all__ = ["Plan", "RFError", "RF_CF32", "RF_CF16", "load_library", "CAND_DTYPE", "STATS_DTYPE"]
@@ -217,20 +218,40 @@ class Plan:
                                          int(cap), _ptr(ncand), None, 0, _stream(stream)), "rf_search")
         return self._collect(cand, ncand, stats, cap)
 
-    def search_segment(self, vis, cap=65536, with_stats=False, ws=None, stream=None, collect=True):
+    def search_segment(self, vis, cap=65536, with_stats=False, ws=None, stream=None, collect=True,
+                       steps=False):
+        """rf_search_segment (fused), or rf_search_segment_steps with steps=True."""
+        torch = _torch()
+        self._check_vis(vis, self.nint)
+        op = RF_OP_SEGMENT_STEPS if steps else RF_OP_SEGMENT
+        if ws is None:
+            ws = self.workspace(op)
+        cand = torch.empty((max(cap, 1), 8), dtype=torch.int32, device=self.device)
+        ncand = torch.zeros(1, dtype=torch.int32, device=self.device)
+        stats = torch.empty((self.n_images, 5), dtype=torch.int32, device=self.device) if with_stats else None
+        fn = _lib.load().rf_search_segment_steps if steps else _lib.load().rf_search_segment
+        _lib.check(fn(self._h, _ptr(vis), _ptr(cand), int(cap), _ptr(ncand), _ptr(stats), _ptr(ws),
+                      ws.numel(), _stream(stream)), "rf_search_segment" + ("_steps" if steps else ""))
+        if not collect:
+            return cand, ncand, stats
+        return self._collect(cand, ncand, stats, cap)
+
+    def profile_segment(self, vis, cap=65536, ws=None, stream=None):
+        """rf_search_segment_profile: one fused search with every kernel launch
+        event-timed.  Returns ({kind: (ms_total, launches)}, candidates, count)."""
         torch = _torch()
         self._check_vis(vis, self.nint)
         if ws is None:
             ws = self.workspace(RF_OP_SEGMENT)
         cand = torch.empty((max(cap, 1), 8), dtype=torch.int32, device=self.device)
         ncand = torch.zeros(1, dtype=torch.int32, device=self.device)
-        stats = torch.empty((self.n_images, 5), dtype=torch.int32, device=self.device) if with_stats else None
-        _lib.check(_lib.load().rf_search_segment(self._h, _ptr(vis), _ptr(cand), int(cap), _ptr(ncand),
-                                                 _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)),
-                   "rf_search_segment")
-        if not collect:
-            return cand, ncand, stats
-        return self._collect(cand, ncand, stats, cap)
+        kt = _lib.KernelTimes()
+        _lib.check(_lib.load().rf_search_segment_profile(self._h, _ptr(vis), _ptr(cand), int(cap), _ptr(ncand),
+                                                         None, _ptr(ws), ws.numel(), _stream(stream),
+                                                         ctypes.byref(kt)), "rf_search_segment_profile")
+        rows, n, _ = self._collect(cand, ncand, None, cap)
+        times = {k: (kt.ms[i], int(kt.launches[i])) for i, k in enumerate(_lib.KERNEL_KINDS)}
+        return times, rows, n
 
     @staticmethod
     def _collect(cand, ncand, stats, cap):

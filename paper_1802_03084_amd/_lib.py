@@ -17,6 +17,7 @@ RF_CF16 = 1
 RF_OP_IMAGE = 1
 RF_OP_SEARCH = 2
 RF_OP_SEGMENT = 3
+RF_OP_SEGMENT_STEPS = 4
 
 c_i32 = ctypes.c_int32
 c_i64 = ctypes.c_int64
@@ -64,6 +65,12 @@ class Candidate(ctypes.Structure):
                 ("sigma", ctypes.c_float)]
 
 
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", c_i64 * 8)]
+
+
+KERNEL_KINDS = ["drs", "rows", "cols", "select", "fallback", "grid"]
+
 assert ctypes.sizeof(Candidate) == 32
 assert ctypes.sizeof(ImageStats) == 20
 assert ctypes.sizeof(ImageTag) == 12
@@ -84,6 +91,9 @@ SIGNATURES = {
     "rf_image": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_size, c_vp]),
     "rf_search": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_size, c_vp]),
     "rf_search_segment": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_size, c_vp]),
+    "rf_search_segment_steps": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_size, c_vp]),
+    "rf_search_segment_profile": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_size, c_vp,
+                                          ctypes.POINTER(KernelTimes)]),
 }
 
 _lib = None

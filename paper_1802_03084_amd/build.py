@@ -23,9 +23,11 @@ COMMON = [
     # keep the compiler from forming packed fp32 VALU ops
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
+    # no implicit fused multiply-adds: kernels that share arithmetic (the fused
+    # and step-chain paths) must round identically; FFT code uses explicit fmaf
+    "-ffp-contract=off",
 ]
-# float64 plan tables must not be contracted into FMAs
-PER_FILE = {"k_tables.hip": ["-ffp-contract=off"]}
+PER_FILE = {}
 
 
 def hipcc():

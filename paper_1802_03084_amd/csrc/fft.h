@@ -19,18 +19,30 @@
 
 namespace rf {
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// The arithmetic below fixes its own fused multiply-adds (contraction is off
+// and fmaf is explicit), so every kernel that inlines these routines rounds
+// identically: the fused and step-chain paths produce bit-identical images.
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) {
+#pragma clang fp contract(off)
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ float2 csub(float2 a, float2 b) {
+#pragma clang fp contract(off)
+  return make_float2(a.x - b.x, a.y - b.y);
+}
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+#pragma clang fp contract(off)
+  return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 crot(float2 x, float c, float s) {
-  return make_float2(x.x * c - x.y * s, x.x * s + x.y * c);
+#pragma clang fp contract(off)
+  return make_float2(__builtin_fmaf(x.x, c, -(x.y * s)), __builtin_fmaf(x.x, s, x.y * c));
 }
 
 // x * exp(+2 pi i e / 16).  e is a compile-time constant at every call site
 // after unrolling, so the switch folds away and trivial rotations cost nothing.
 __device__ __forceinline__ float2 rot16(float2 x, int e) {
+#pragma clang fp contract(off)
   constexpr float c1 = 0.92387953251128675613f;  // cos(pi/8)
   constexpr float s1 = 0.38268343236508977173f;  // sin(pi/8)
   constexpr float h = 0.70710678118654752440f;   // cos(pi/4)
@@ -88,7 +100,13 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
   for (int i = 0; i < R; ++i) v[i] = t[i];
 }
 
-template <int N, int R, int NS, int F, int NT, int STRIDE>
+// Padded LDS index: one spare element after every 2^PS, so that the stride-R
+// writes of the first pass (and the strided column gathers) spread over the
+// LDS banks instead of piling onto one.
+template <int PS>
+__device__ __forceinline__ int pidx(int i) { return i + (i >> PS); }
+
+template <int N, int R, int NS, int F, int NT, int STRIDE, int PS>
 __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *tw, int tid) {
   constexpr int NB = N / R;
   constexpr int TOT = F * NB;
@@ -99,9 +117,9 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *tw, int
     const int idx = tid + q * NT;
     if ((TOT % NT) == 0 || idx < TOT) {
       const int f = idx / NB, j = idx % NB;
-      const float2 *src = buf + f * STRIDE + j;
+      const float2 *src = buf + f * STRIDE;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = src[r * NB];
+      for (int r = 0; r < R; ++r) v[q][r] = src[pidx<PS>(j + r * NB)];
       if (NS > 1) {
         const int jm = j % NS;
 #pragma unroll
@@ -116,41 +134,63 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *tw, int
     const int idx = tid + q * NT;
     if ((TOT % NT) == 0 || idx < TOT) {
       const int f = idx / NB, j = idx % NB;
-      float2 *dst = buf + f * STRIDE + (j / NS) * NS * R + (j % NS);
+      float2 *dst = buf + f * STRIDE;
+      const int d0 = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * NS] = v[q][r];
+      for (int r = 0; r < R; ++r) dst[pidx<PS>(d0 + r * NS)] = v[q][r];
     }
   }
   __syncthreads();
 }
 
-// Inverse (exp(+i)) unnormalised FFT of F sequences of length N in LDS.
-// Callers synchronise before (inputs written) and may read after return.
+// Radix schedule and LDS padding for each supported N.
+template <int N>
+struct FftShape {
+  static_assert(N >= 64 && N <= 2048 && (N & (N - 1)) == 0, "N must be 2^k in [64, 2048]");
+  static constexpr int PS = (N == 512) ? 3 : 4;  // log2 of the first radix
+  static constexpr int PADDED = N + (N >> PS);   // padded length of one sequence
+};
+
+// Inverse (exp(+i)) unnormalised FFT of F sequences of length N in LDS, each
+// stored padded (element i at pidx(i)) from buf + f * STRIDE.  Callers
+// synchronise before (inputs written) and may read after return.
 template <int N, int F, int NT, int STRIDE>
 __device__ __forceinline__ void fft_inverse(float2 *buf, const float2 *tw, int tid) {
-  static_assert(N >= 64 && N <= 2048 && (N & (N - 1)) == 0, "N must be 2^k in [64, 2048]");
+  constexpr int PS = FftShape<N>::PS;
   if constexpr (N == 64) {
-    stockham_pass<N, 16, 1, F, NT, STRIDE>(buf, tw, tid);
-    stockham_pass<N, 4, 16, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 16, 1, F, NT, STRIDE, PS>(buf, tw, tid);
+    stockham_pass<N, 4, 16, F, NT, STRIDE, PS>(buf, tw, tid);
   } else if constexpr (N == 128) {
-    stockham_pass<N, 16, 1, F, NT, STRIDE>(buf, tw, tid);
-    stockham_pass<N, 8, 16, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 16, 1, F, NT, STRIDE, PS>(buf, tw, tid);
+    stockham_pass<N, 8, 16, F, NT, STRIDE, PS>(buf, tw, tid);
   } else if constexpr (N == 256) {
-    stockham_pass<N, 16, 1, F, NT, STRIDE>(buf, tw, tid);
-    stockham_pass<N, 16, 16, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 16, 1, F, NT, STRIDE, PS>(buf, tw, tid);
+    stockham_pass<N, 16, 16, F, NT, STRIDE, PS>(buf, tw, tid);
   } else if constexpr (N == 512) {
-    stockham_pass<N, 8, 1, F, NT, STRIDE>(buf, tw, tid);
-    stockham_pass<N, 8, 8, F, NT, STRIDE>(buf, tw, tid);
-    stockham_pass<N, 8, 64, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 8, 1, F, NT, STRIDE, PS>(buf, tw, tid);
+    stockham_pass<N, 8, 8, F, NT, STRIDE, PS>(buf, tw, tid);
+    stockham_pass<N, 8, 64, F, NT, STRIDE, PS>(buf, tw, tid);
   } else if constexpr (N == 1024) {
-    stockham_pass<N, 16, 1, F, NT, STRIDE>(buf, tw, tid);
-    stockham_pass<N, 16, 16, F, NT, STRIDE>(buf, tw, tid);
-    stockham_pass<N, 4, 256, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 16, 1, F, NT, STRIDE, PS>(buf, tw, tid);
+    stockham_pass<N, 16, 16, F, NT, STRIDE, PS>(buf, tw, tid);
+    stockham_pass<N, 4, 256, F, NT, STRIDE, PS>(buf, tw, tid);
   } else {
-    stockham_pass<N, 16, 1, F, NT, STRIDE>(buf, tw, tid);
-    stockham_pass<N, 16, 16, F, NT, STRIDE>(buf, tw, tid);
-    stockham_pass<N, 8, 256, F, NT, STRIDE>(buf, tw, tid);
+    stockham_pass<N, 16, 1, F, NT, STRIDE, PS>(buf, tw, tid);
+    stockham_pass<N, 16, 16, F, NT, STRIDE, PS>(buf, tw, tid);
+    stockham_pass<N, 8, 256, F, NT, STRIDE, PS>(buf, tw, tid);
   }
+}
+
+// Z value of the paired Hermitian transform at grid position (v, u):
+//   Z = s/2 [G_a(v,u) + conj G_a(-v,-u) + i (G_b(v,u) + conj G_b(-v,-u))]
+// with s = (-1)^(u+v) and sg = s/2.  Evaluated as the (v,u) term plus the
+// mirrored term in this fixed order, so that every caller (dense grids or
+// gathered cells) produces bit-identical values.
+__device__ __forceinline__ float2 zval(float2 a, float2 am, float2 b, float2 bm, float sg) {
+#pragma clang fp contract(off)
+  const float x = sg * (a.x - b.y) + sg * (am.x + bm.y);
+  const float y = sg * (a.y + b.x) + sg * (bm.x - am.y);
+  return make_float2(x, y);
 }
 
 // Launch shapes of the two imaging passes for image side N.
@@ -158,12 +198,13 @@ template <int N>
 struct RowCfg {
   static constexpr int NT = 512;
   static constexpr int F = (8192 / N) < 64 ? (8192 / N) : 64;  // rows per workgroup
+  static constexpr int STRIDE = FftShape<N>::PADDED;
 };
 template <int N>
 struct ColCfg {
   static constexpr int NT = 1024;
   static constexpr int COLS = (16384 / N) < N ? (16384 / N) : N;  // columns per workgroup
-  static constexpr int STRIDE = N + 1;                            // padded column stride
+  static constexpr int STRIDE = FftShape<N>::PADDED + 1;          // odd: spreads the transpose
 };
 
 }  // namespace rf

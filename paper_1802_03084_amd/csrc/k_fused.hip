@@ -1,0 +1,960 @@
+// Fused whole-segment search (Law et al. 2018, section 3.1 and Figure 2):
+// per DM trial, one pass over the segment dedisperses, resamples to every
+// trial width and forms Stokes I; per pair of images the row pass gathers uv
+// cells straight from those samples and transforms the rows; the column pass
+// transforms the columns and reduces every image to its peak and to the few
+// pixels that can hold the median; a last kernel picks the exact median and
+// thresholds.  No dense grid and no image ever reaches HBM.
+//
+// Exact median without the image: the image rms is known before the column
+// pass (Parseval: sum img^2 = N^2 / W^2 * sum |H|^2 over the Hermitian part
+// H of the grid), and for noise images median|img| / rms sits within 0.2 %
+// of 0.6745.  The column pass therefore counts pixels below a bracket
+// 0.6745 rms (1 -/+ 1 %) and keeps those inside it; if the rank of the lower
+// median falls inside the bracket the kept values contain it and the result
+// is exact.  Otherwise (a bright source shifts the rms, or a region of kept
+// values overflows) the image is recomputed by the step chain after the
+// segment, so every reported sigma is the exact lower median.
+//
+// Every value is computed with the same operations in the same order as the
+// step chain (rf_dedisperse -> rf_resample -> rf_grid -> rf_image ->
+// rf_search), so both paths give bit-identical images.
+#include "rf_internal.h"
+#include "fft.h"
+
+#include <hip/hip_fp16.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+namespace {
+
+using namespace rf;
+
+constexpr int kMaxW = 8;               // widths handled by one pass over the segment
+constexpr float kMedOverRms = 0.6745f; // median |x| / rms of a zero-mean Gaussian
+constexpr float kBracket = 0.01f;      // half-width of the median bracket (relative)
+constexpr int kDrsThreads = 256;
+constexpr int kSelThreads = 256;
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct WidthSet {
+  int w[kMaxW];
+  int nk[kMaxW];     // images of each width (= nint / w)
+  float2 *out[kMaxW];
+  int nw;
+};
+
+struct ColPart {   // per (image, column workgroup)
+  float maxv;
+  int32_t maxi;
+  uint32_t cnt_lo;
+  uint32_t n;      // values inside the bracket (may exceed the region size)
+};
+
+__device__ __forceinline__ bool better(float v, int i, float bv, int bi) {
+  return v > bv || (v == bv && i < bi);
+}
+
+// ------------------------------------------------------------------ drs
+__device__ __forceinline__ void load_pols(const float2 *vis, size_t e, int P, float2 &a,
+                                          float2 &b) {
+  if (P == 2) {
+    const float4 x = *reinterpret_cast<const float4 *>(vis + 2 * e);
+    a = make_float2(x.x, x.y);
+    b = make_float2(x.z, x.w);
+  } else {
+    a = vis[e];
+  }
+}
+__device__ __forceinline__ void load_pols(const __half2 *vis, size_t e, int P, float2 &a,
+                                          float2 &b) {
+  if (P == 2) {
+    const uint2 x = *reinterpret_cast<const uint2 *>(vis + 2 * e);
+    a = __half22float2(*reinterpret_cast<const __half2 *>(&x.x));
+    b = __half22float2(*reinterpret_cast<const __half2 *>(&x.y));
+  } else {
+    a = __half22float2(vis[e]);
+  }
+}
+
+// Dedisperse + boxcar-resample to every width in `ws` + Stokes I, one thread
+// per (baseline, channel) walking a chunk of integrations that starts at a
+// multiple of every width.  Sums run per polarisation in increasing time and
+// are divided by the width before the polarisations are averaged, exactly as
+// rf_resample followed by rf_grid's Stokes I.  Output per width:
+// VI_w[k][bc], coalesced along bc.
+template <typename Ein, int P>
+__global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis,
+                                                     const int32_t *__restrict__ delay, int nint,
+                                                     int nbc, int nchan, int tchunk, WidthSet ws) {
+  const int bc = blockIdx.x * kDrsThreads + threadIdx.x;
+  if (bc >= nbc) return;
+  const int d = delay[bc % nchan];
+  const int t0 = blockIdx.y * tchunk;
+  const int t1 = min(nint, t0 + tchunk);
+  float2 a0[kMaxW], a1[kMaxW];
+  int cnt[kMaxW];
+#pragma unroll
+  for (int j = 0; j < kMaxW; ++j) {
+    a0[j] = make_float2(0.f, 0.f);
+    a1[j] = a0[j];
+    cnt[j] = 0;
+  }
+  for (int t = t0; t < t1; ++t) {
+    const int src = t + d;
+    float2 v0 = make_float2(0.f, 0.f), v1 = v0;
+    if (src < nint) load_pols(vis, (size_t)src * nbc + bc, P, v0, v1);
+#pragma unroll
+    for (int j = 0; j < kMaxW; ++j) {
+      if (j < ws.nw) {
+        a0[j].x += v0.x;
+        a0[j].y += v0.y;
+        if (P == 2) {
+          a1[j].x += v1.x;
+          a1[j].y += v1.y;
+        }
+        if (++cnt[j] == ws.w[j]) {
+          const int k = (t + 1) / ws.w[j] - 1;
+          const float fw = (float)ws.w[j];
+          float2 vi;
+          if (P == 2) {
+            const float r0x = a0[j].x / fw, r0y = a0[j].y / fw;
+            const float r1x = a1[j].x / fw, r1y = a1[j].y / fw;
+            vi = make_float2((r0x + r1x) * 0.5f, (r0y + r1y) * 0.5f);
+          } else {
+            vi = make_float2(a0[j].x / fw, a0[j].y / fw);
+          }
+          ws.out[j][(size_t)k * nbc + bc] = vi;
+          a0[j] = make_float2(0.f, 0.f);
+          a1[j] = a0[j];
+          cnt[j] = 0;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ rows
+// Gridding as a gather: CV[i][c] = sum of the Stokes I samples of uv cell c
+// for image i of a batch, in the plan's contributor order (the same sums as
+// rf_grid).  All blocks of one image run on one XCD (blocks are dealt to the
+// eight XCDs round robin), so the image's samples stay in that XCD's L2 while
+// its cells gather them.
+constexpr int kCellThreads = 256;
+
+__global__ __launch_bounds__(kCellThreads) void k_cellsum(
+    const float2 *__restrict__ vi, int nbc, int k0, int nimg, int n_cells, int bpi,
+    const int32_t *__restrict__ coff, const int32_t *__restrict__ contrib,
+    float2 *__restrict__ cv) {
+  const int b = blockIdx.x, xcd = b & 7, local = b >> 3;
+  const int il = (local / bpi) * 8 + xcd;  // image within the batch
+  const int c = (local % bpi) * kCellThreads + threadIdx.x;
+  if (il >= nimg || c >= n_cells) return;
+  const float2 *v = vi + (size_t)(k0 + il) * nbc;
+  float2 acc = make_float2(0.f, 0.f);
+  const int e = coff[c + 1];
+  int q = coff[c];
+  for (; q + 4 <= e; q += 4) {  // four independent loads in flight
+    const int b0 = contrib[q], b1 = contrib[q + 1], b2 = contrib[q + 2], b3 = contrib[q + 3];
+    const float2 x0 = v[b0], x1 = v[b1], x2 = v[b2], x3 = v[b3];
+    acc.x += x0.x;
+    acc.y += x0.y;
+    acc.x += x1.x;
+    acc.y += x1.y;
+    acc.x += x2.x;
+    acc.y += x2.y;
+    acc.x += x3.x;
+    acc.y += x3.y;
+  }
+  for (; q < e; ++q) {
+    const float2 x = v[contrib[q]];
+    acc.x += x.x;
+    acc.y += x.y;
+  }
+  cv[(size_t)il * n_cells + c] = acc;
+}
+
+// Row pass.  A workgroup takes one row pair {v, -v} for a block of PBW image
+// pairs: it reads the cell sums of both rows (contiguous in cell order), forms
+// Z on both rows (row -v is the conjugate-mirror combination of the same
+// cells), transforms the 2 PBW rows and writes them.  It also writes each
+// image's share of sum |H|^2 (Parseval) for the median bracket of the column
+// pass.
+template <int N>
+struct RowPairCfg {
+  static constexpr int NT = 512;
+  static constexpr int PBW = N >= 2048 ? 4 : 8;  // image pairs per workgroup
+  static constexpr int F = 2 * PBW;              // transforms per workgroup
+  static constexpr int STRIDE = FftShape<N>::PADDED;
+};
+
+template <int N>
+__global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
+    const float2 *__restrict__ cv, int n_cells, int nk, int p0, int pbn,
+    const int32_t *__restrict__ rp_row, const int32_t *__restrict__ rp_sa,
+    const int32_t *__restrict__ rp_sb, int n_rp, int n_rows, const int32_t *__restrict__ zs_off,
+    const int32_t *__restrict__ zs_u, const int32_t *__restrict__ zs_ck,
+    const int32_t *__restrict__ zs_cmk, const float2 *__restrict__ tw_g, float2 *__restrict__ M,
+    float *__restrict__ epart) {
+  constexpr int PBW = RowPairCfg<N>::PBW, F = RowPairCfg<N>::F, NT = RowPairCfg<N>::NT;
+  constexpr int S = RowPairCfg<N>::STRIDE, PS = FftShape<N>::PS;
+  __shared__ float2 buf[F * S];
+  __shared__ float2 tw[N];
+  __shared__ float s_e[2 * PBW];
+  const int rp = blockIdx.x % n_rp;
+  const int pb0 = (blockIdx.x / n_rp) * PBW;  // first pair of this block, batch-local
+  const int tid = threadIdx.x;
+  const int r = rp_row[rp];
+  const int rm = (N - r) & (N - 1);
+  const bool two = rm != r;
+  for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
+  for (int i = tid; i < F * S; i += NT) buf[i] = make_float2(0.f, 0.f);
+  if (tid < 2 * PBW) s_e[tid] = 0.f;
+  __syncthreads();
+  const int z0 = zs_off[rp], nz = zs_off[rp + 1] - z0;
+  const float ew = two ? 0.5f : 0.25f;  // |H|^2 = |.|^2/4, counted twice for a row pair
+  for (int it = tid; it < nz * PBW; it += NT) {
+    const int z = z0 + it % nz, pp = it / nz;  // positions fastest: contiguous cells
+    const int pl = pb0 + pp;
+    if (pl >= pbn) continue;
+    const int ia = 2 * (p0 + pl);
+    const bool hasb = ia + 1 < nk;
+    const int ib = 2 * pl;  // image a within the batch
+    const int u = zs_u[z], ck = zs_ck[z], cmk = zs_cmk[z];
+    const float2 zero = make_float2(0.f, 0.f);
+    const float2 *ca = cv + (size_t)ib * n_cells;
+    const float2 *cb = ca + n_cells;
+    const float2 ga = ck >= 0 ? ca[ck] : zero;
+    const float2 gam = cmk >= 0 ? ca[cmk] : zero;
+    const float2 gb = (hasb && ck >= 0) ? cb[ck] : zero;
+    const float2 gbm = (hasb && cmk >= 0) ? cb[cmk] : zero;
+    const float sg = ((r + u) & 1) ? -0.5f : 0.5f;
+    buf[pp * S + pidx<PS>(u)] = zval(ga, gam, gb, gbm, sg);
+    if (two) buf[(PBW + pp) * S + pidx<PS>((N - u) & (N - 1))] = zval(gam, ga, gbm, gb, sg);
+    const float hax = ga.x + gam.x, hay = ga.y - gam.y;
+    const float hbx = gb.x + gbm.x, hby = gb.y - gbm.y;
+    atomicAdd(&s_e[2 * pp + 0], ew * (hax * hax + hay * hay));
+    atomicAdd(&s_e[2 * pp + 1], ew * (hbx * hbx + hby * hby));
+  }
+  __syncthreads();
+  if (tid < 2 * PBW && pb0 + tid / 2 < pbn)
+    epart[((size_t)(pb0 + tid / 2) * n_rp + rp) * 2 + (tid & 1)] = s_e[tid];
+  fft_inverse<N, F, NT, S>(buf, tw, tid);
+  const int sa = rp_sa[rp], sb = rp_sb[rp];
+  for (int e = tid; e < F * N; e += NT) {
+    const int f = e / N, x = e % N;
+    const int side = f / PBW, pp = f % PBW;
+    const int pl = pb0 + pp;
+    if (pl >= pbn || (side == 1 && !two)) continue;
+    const int slot = side ? sb : sa;
+    M[((size_t)pl * n_rows + slot) * N + x] = buf[f * S + pidx<PS>(x)];
+  }
+}
+
+// ------------------------------------------------------------------ columns
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
+    const float2 *__restrict__ M, int n_rows, const int32_t *__restrict__ row_slot, int nimg_w,
+    int p0, int pbn, float inv_w, const float2 *__restrict__ tw_g,
+    const float *__restrict__ epart, int n_rp, ColPart *__restrict__ part,
+    float *__restrict__ list, int reg) {
+  constexpr int COLS = ColCfg<N>::COLS, NT = ColCfg<N>::NT, S = ColCfg<N>::STRIDE;
+  constexpr int PS = FftShape<N>::PS;
+  constexpr int CB = N / COLS;
+  constexpr int NW = NT / 64;
+  __shared__ float2 buf[COLS * S];
+  __shared__ float2 tw[N];
+  __shared__ float s_br[4];
+  __shared__ uint32_t s_n[2];
+  __shared__ float w_v[2][NW];
+  __shared__ int32_t w_i[2][NW];
+  __shared__ uint32_t w_c[2][NW];
+  const int pl = blockIdx.x / CB;
+  const int cb = blockIdx.x % CB;
+  if (pl >= pbn) return;
+  const int tid = threadIdx.x;
+  const int x0 = cb * COLS;
+  for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
+  if (tid < 64) {
+    float ea = 0.f, eb = 0.f;
+    for (int r = tid; r < n_rp; r += 64) {
+      ea += epart[2 * ((size_t)pl * n_rp + r) + 0];
+      eb += epart[2 * ((size_t)pl * n_rp + r) + 1];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      ea += __shfl_xor(ea, o, 64);
+      eb += __shfl_xor(eb, o, 64);
+    }
+    if (tid < 2) {
+      const float m = kMedOverRms * (sqrtf(tid == 0 ? ea : eb) * inv_w);
+      s_br[2 * tid + 0] = m * (1.0f - kBracket);
+      s_br[2 * tid + 1] = m * (1.0f + kBracket);
+      s_n[tid] = 0;
+    }
+  }
+  const float2 *Mp = M + (size_t)pl * n_rows * N + x0;
+  for (int e = tid; e < N * COLS; e += NT) {
+    const int r = e / COLS, x = e % COLS;
+    const int slot = row_slot[r];
+    buf[x * S + pidx<PS>(r)] = slot >= 0 ? Mp[(size_t)slot * N + x] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_inverse<N, COLS, NT, S>(buf, tw, tid);
+  const bool hasb = 2 * (p0 + pl) + 1 < nimg_w;
+  const float lo_a = s_br[0], hi_a = s_br[1], lo_b = s_br[2], hi_b = s_br[3];
+  float *la = list + ((size_t)(2 * pl) * CB + cb) * reg;
+  float *lb = list + ((size_t)(2 * pl + 1) * CB + cb) * reg;
+  float bva = -__builtin_inff(), bvb = -__builtin_inff();
+  int bia = 0x7fffffff, bib = 0x7fffffff;
+  uint32_t ca = 0, cbn = 0;
+  for (int e = tid; e < N * COLS; e += NT) {
+    const int y = e / COLS, x = e % COLS;
+    const float2 v = buf[x * S + pidx<PS>(y)];
+    const int idx = y * N + x0 + x;
+    const float pa = v.x * inv_w;
+    if (better(pa, idx, bva, bia)) {
+      bva = pa;
+      bia = idx;
+    }
+    const float aa = fabsf(pa);
+    if (aa < lo_a) {
+      ++ca;
+    } else if (aa < hi_a) {
+      const uint32_t pos = atomicAdd(&s_n[0], 1u);
+      if (pos < (uint32_t)reg) la[pos] = aa;
+    }
+    if (hasb) {
+      const float pb = v.y * inv_w;
+      if (better(pb, idx, bvb, bib)) {
+        bvb = pb;
+        bib = idx;
+      }
+      const float ab = fabsf(pb);
+      if (ab < lo_b) {
+        ++cbn;
+      } else if (ab < hi_b) {
+        const uint32_t pos = atomicAdd(&s_n[1], 1u);
+        if (pos < (uint32_t)reg) lb[pos] = ab;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const float ova = __shfl_xor(bva, o, 64);
+    const int oia = __shfl_xor(bia, o, 64);
+    if (better(ova, oia, bva, bia)) {
+      bva = ova;
+      bia = oia;
+    }
+    const float ovb = __shfl_xor(bvb, o, 64);
+    const int oib = __shfl_xor(bib, o, 64);
+    if (better(ovb, oib, bvb, bib)) {
+      bvb = ovb;
+      bib = oib;
+    }
+    ca += __shfl_xor(ca, o, 64);
+    cbn += __shfl_xor(cbn, o, 64);
+  }
+  const int wid = tid >> 6;
+  if ((tid & 63) == 0) {
+    w_v[0][wid] = bva;
+    w_i[0][wid] = bia;
+    w_c[0][wid] = ca;
+    w_v[1][wid] = bvb;
+    w_i[1][wid] = bib;
+    w_c[1][wid] = cbn;
+  }
+  __syncthreads();
+  if (tid < 2 && (tid == 0 || hasb)) {
+    float v = w_v[tid][0];
+    int i = w_i[tid][0];
+    uint32_t c = w_c[tid][0];
+    for (int w = 1; w < NW; ++w) {
+      if (better(w_v[tid][w], w_i[tid][w], v, i)) {
+        v = w_v[tid][w];
+        i = w_i[tid][w];
+      }
+      c += w_c[tid][w];
+    }
+    ColPart cp;
+    cp.maxv = v;
+    cp.maxi = i;
+    cp.cnt_lo = c;
+    cp.n = s_n[tid];
+    part[(size_t)(2 * pl + tid) * CB + cb] = cp;
+  }
+}
+
+// ------------------------------------------------------------------ select
+constexpr int kBins = 2048;
+
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t *wsum) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  uint32_t add = 0;
+  for (int w = 0; w < wid; ++w) add += wsum[w];
+  __syncthreads();
+  return inc - x + add;
+}
+
+// Finds the bin of hist[kBins] that holds `rank`; 8 bins per thread.
+__device__ __forceinline__ void sel_bin(const uint32_t *hist, uint32_t rank, uint32_t *wsum,
+                                        uint32_t *sel) {
+  const int t = threadIdx.x;
+  uint32_t h[8], tot = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    h[i] = hist[8 * t + i];
+    tot += h[i];
+  }
+  uint32_t pre = block_excl_scan256(tot, wsum);
+  if (rank >= pre && rank < pre + tot) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (rank >= pre && rank < pre + h[i]) {
+        sel[0] = 8 * t + i;
+        sel[1] = rank - pre;
+      }
+      pre += h[i];
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kSelThreads) void k_select(
+    const ColPart *__restrict__ part, const float *__restrict__ list, int cbn, int reg,
+    int nimg_w, int p0, int pbn, int npix, int dm_idx, int width_idx, int width,
+    int64_t stat_base, rf_image_stats *__restrict__ stats, rf_candidate *__restrict__ cand,
+    int cap, int32_t *__restrict__ ncand, int32_t *__restrict__ fb_count,
+    int32_t *__restrict__ fb_list, float thr, int t_begin, int t_end) {
+  __shared__ uint32_t hist[kBins];
+  __shared__ uint32_t cnt[256];
+  __shared__ uint32_t wsum[kSelThreads / 64];
+  __shared__ uint32_t sel[2];
+  __shared__ float w_v[kSelThreads / 64];
+  __shared__ int32_t w_i[kSelThreads / 64];
+  __shared__ uint32_t w_lo[kSelThreads / 64], w_n[kSelThreads / 64], w_o[kSelThreads / 64];
+  __shared__ float s_v;
+  __shared__ int32_t s_i;
+  __shared__ uint32_t s_lo, s_n;
+  __shared__ int s_ovf;
+  const int il = blockIdx.x;
+  const int pl = il >> 1;
+  const int k = 2 * (p0 + pl) + (il & 1);
+  if (pl >= pbn || k >= nimg_w) return;
+  const int tid = threadIdx.x;
+  const ColPart *pp = part + (size_t)il * cbn;
+  {  // combine the column workgroups' records (cbn <= 256 = kSelThreads)
+    float v = -__builtin_inff();
+    int32_t i = 0x7fffffff;
+    uint32_t lo = 0, n = 0, ovf = 0;
+    if (tid < cbn) {
+      const ColPart c = pp[tid];
+      v = c.maxv;
+      i = c.maxi;
+      lo = c.cnt_lo;
+      n = min(c.n, (uint32_t)reg);
+      ovf = c.n > (uint32_t)reg;
+      cnt[tid] = n;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const float ov = __shfl_xor(v, o, 64);
+      const int32_t oi = __shfl_xor(i, o, 64);
+      if (better(ov, oi, v, i)) {
+        v = ov;
+        i = oi;
+      }
+      lo += __shfl_xor(lo, o, 64);
+      n += __shfl_xor(n, o, 64);
+      ovf |= __shfl_xor(ovf, o, 64);
+    }
+    const int wid = tid >> 6;
+    if ((tid & 63) == 0) {
+      w_v[wid] = v;
+      w_i[wid] = i;
+      w_lo[wid] = lo;
+      w_n[wid] = n;
+      w_o[wid] = ovf;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < kSelThreads / 64; ++w) {
+        if (better(w_v[w], w_i[w], v, i)) {
+          v = w_v[w];
+          i = w_i[w];
+        }
+        lo += w_lo[w];
+        n += w_n[w];
+        ovf |= w_o[w];
+      }
+      s_v = v;
+      s_i = i;
+      s_lo = lo;
+      s_n = n;
+      s_ovf = (int)ovf;
+    }
+  }
+  __syncthreads();
+  const float peak = s_v;
+  const int32_t pidx_ = s_i;
+  const uint32_t rank = (uint32_t)(((size_t)npix * npix - 1) / 2);
+  float med;
+  if (peak == 0.f && s_lo == 0 && s_n == 0) {
+    med = 0.f;  // identically zero image (every pixel equals the zero peak)
+  } else if (!s_ovf && s_lo <= rank && rank < s_lo + s_n) {
+    uint32_t r = rank - s_lo;
+    const float *lp = list + (size_t)il * cbn * reg;
+    uint32_t prefix = 0;
+    // three radix passes over the kept values: bits 30..20, 19..9, 8..0
+    for (int pass = 0; pass < 3; ++pass) {
+      for (int i = tid; i < kBins; i += kSelThreads) hist[i] = 0;
+      __syncthreads();
+      for (int g = 0; g < cbn; ++g) {
+        const uint32_t ng = cnt[g];
+        for (uint32_t e = tid; e < ng; e += kSelThreads) {
+          const uint32_t key = __float_as_uint(lp[(size_t)g * reg + e]);
+          if (pass == 0) {
+            atomicAdd(&hist[key >> 20], 1u);
+          } else if (pass == 1) {
+            if ((key >> 20) == prefix) atomicAdd(&hist[(key >> 9) & 2047u], 1u);
+          } else {
+            if ((key >> 9) == prefix) atomicAdd(&hist[key & 511u], 1u);
+          }
+        }
+      }
+      __syncthreads();
+      sel_bin(hist, r, wsum, sel);
+      const uint32_t bin = sel[0];
+      r = sel[1];
+      __syncthreads();
+      prefix = pass == 0 ? bin : (pass == 1 ? ((prefix << 11) | bin) : ((prefix << 9) | bin));
+    }
+    med = __uint_as_float(prefix);
+  } else {
+    if (tid == 0) {
+      const int slot = atomicAdd(fb_count, 1);
+      fb_list[slot] = (int32_t)(stat_base + k);
+    }
+    return;
+  }
+  if (tid == 0) {
+    const float sigma = 1.4826f * med;
+    const float snr = sigma > 0.f ? peak / sigma : 0.f;
+    const int x = pidx_ % npix, y = pidx_ / npix;
+    if (stats) {
+      rf_image_stats st;
+      st.peak = peak;
+      st.sigma = sigma;
+      st.snr = snr;
+      st.x = x;
+      st.y = y;
+      stats[stat_base + k] = st;
+    }
+    const int t_int = k * width;
+    if (snr > thr && t_int >= t_begin && t_int < t_end) {
+      const int slot = atomicAdd(ncand, 1);
+      if (slot < cap) {
+        rf_candidate c;
+        c.dm_idx = dm_idx;
+        c.width_idx = width_idx;
+        c.t_int = t_int;
+        c.x = x;
+        c.y = y;
+        c.snr = snr;
+        c.peak = peak;
+        c.sigma = sigma;
+        cand[slot] = c;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ host side
+struct Shape {
+  int pbw, cbp, pb, reg;
+};
+
+template <int N>
+Shape shape_n(const rf_plan *p) {
+  Shape s;
+  s.pbw = RowPairCfg<N>::PBW;
+  s.cbp = N / ColCfg<N>::COLS;
+  s.reg = N * ColCfg<N>::COLS / 16;
+  // pairs per batch: keep the row-transformed batch (~128 MB) cache-resident
+  const size_t per_pair = (size_t)std::max(1, p->n_rows) * N * sizeof(float2);
+  const int pb = (int)std::max<size_t>(s.pbw, ((size_t)128 << 20) / per_pair);
+  s.pb = std::min(64, (pb / s.pbw) * s.pbw);
+  return s;
+}
+
+Shape shape_of(const rf_plan *p) {
+  switch (p->npix) {
+    case 64: return shape_n<64>(p);
+    case 128: return shape_n<128>(p);
+    case 256: return shape_n<256>(p);
+    case 512: return shape_n<512>(p);
+    case 1024: return shape_n<1024>(p);
+    default: return shape_n<2048>(p);
+  }
+}
+
+// Per-batch records are double-buffered: the select of batch b runs on a side
+// stream while batch b+1 is transformed.
+struct Layout {
+  size_t vi, cv, m, epart[2], part[2], list[2], fb, dd, rs, grid, img, mws, total;
+  std::vector<size_t> vi_off;  // per width, in float2 units
+};
+
+Layout layout_of(const rf_plan *p) {
+  Layout L;
+  const Shape sh = shape_of(p);
+  const size_t nbc = (size_t)p->nbl * p->nchan;
+  const size_t np2 = (size_t)p->npix * p->npix;
+  size_t o = 0, vi_elems = 0;
+  for (int j = 0; j < p->nwidth; ++j) {
+    L.vi_off.push_back(vi_elems);
+    vi_elems += (size_t)(p->nint / p->width[j]) * nbc;
+  }
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  L.vi = take(vi_elems * sizeof(float2));
+  L.cv = take((size_t)2 * sh.pb * std::max(1, p->n_cells) * sizeof(float2));
+  L.m = take((size_t)sh.pb * p->n_rows * p->npix * sizeof(float2));
+  for (int d = 0; d < 2; ++d) {
+    L.epart[d] = take((size_t)sh.pb * std::max(1, p->n_rp) * 2 * sizeof(float));
+    L.part[d] = take((size_t)2 * sh.pb * sh.cbp * sizeof(ColPart));
+    L.list[d] = take((size_t)2 * sh.pb * sh.cbp * sh.reg * sizeof(float));
+  }
+  L.fb = take(((size_t)p->n_images + 1) * sizeof(int32_t));
+  // buffers of the exact fallback (step chain on one image pair)
+  const size_t sb = p->vis_dtype == RF_CF32 ? 8 : 4;
+  L.dd = take((size_t)p->nint * nbc * p->npol * sb);
+  L.rs = take((size_t)p->nint * nbc * p->npol * 8);
+  L.grid = take(2 * np2 * 8);
+  L.img = take(2 * np2 * 4);
+  L.mws = take(image_ws_bytes(p, 2));
+  L.total = o;
+  return L;
+}
+
+// Optional event timing of every launch (rf_search_segment_profile).  When
+// timing, everything runs on the caller's stream so durations do not overlap.
+struct Timer {
+  rf_kernel_times *kt = nullptr;
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> kind;
+  size_t used = 0;
+  hipError_t mark(int k) {  // call before (k >= 0) and after (k = -1) a launch
+    if (!kt) return hipSuccess;
+    if (used == pool.size()) {
+      hipEvent_t e;
+      const hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) return err;
+      pool.push_back(e);
+    }
+    if (k >= 0) kind.push_back(k);
+    return hipEventRecord(pool[used++], s);
+  }
+  hipError_t flush() {
+    if (!kt || used == 0) return hipSuccess;
+    hipError_t err = hipStreamSynchronize(s);
+    if (err != hipSuccess) return err;
+    for (size_t q = 0; q + 1 < used; q += 2) {
+      float ms = 0.f;
+      err = hipEventElapsedTime(&ms, pool[q], pool[q + 1]);
+      if (err != hipSuccess) return err;
+      kt->ms[kind[q / 2]] += ms;
+      kt->launches[kind[q / 2]] += 1;
+    }
+    used = 0;
+    kind.clear();
+    return hipSuccess;
+  }
+  ~Timer() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+#define RF_TIMED(tm, k, launch)          \
+  do {                                   \
+    RF_HIP_TRY((tm)->mark(k));           \
+    launch;                              \
+    RF_HIP_TRY(hipGetLastError());       \
+    RF_HIP_TRY((tm)->mark(-1));          \
+  } while (0)
+
+// Side stream and events that overlap each batch's select with the next
+// batch's transforms.  Created per call; default priority.
+struct Overlap {
+  hipStream_t side = nullptr;
+  hipEvent_t cols_done[2] = {nullptr, nullptr}, sel_done[2] = {nullptr, nullptr};
+  bool used[2] = {false, false};
+  hipError_t init() {
+    hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+    for (int d = 0; d < 2 && e == hipSuccess; ++d) {
+      e = hipEventCreateWithFlags(&cols_done[d], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&sel_done[d], hipEventDisableTiming);
+    }
+    return e;
+  }
+  ~Overlap() {
+    for (int d = 0; d < 2; ++d) {
+      if (cols_done[d]) (void)hipEventDestroy(cols_done[d]);
+      if (sel_done[d]) (void)hipEventDestroy(sel_done[d]);
+    }
+    if (side) (void)hipStreamDestroy(side);
+  }
+};
+
+template <int N>
+rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_w, int p0,
+                  int pbn, int dm_idx, int width_idx, int width, int64_t stat_base, char *ws,
+                  const Layout &L, int db, rf_image_stats *stats, rf_candidate *cand, int cap,
+                  int32_t *ncand, hipStream_t s, Timer *tm, Overlap *ov) {
+  float2 *M = (float2 *)(ws + L.m);
+  float2 *cv = (float2 *)(ws + L.cv);
+  float *epart = (float *)(ws + L.epart[db]);
+  ColPart *part = (ColPart *)(ws + L.part[db]);
+  float *list = (float *)(ws + L.list[db]);
+  int32_t *fb = (int32_t *)(ws + L.fb);
+  // the select that last used this buffer set must be done with it
+  if (ov && ov->used[db]) RF_HIP_TRY(hipStreamWaitEvent(s, ov->sel_done[db], 0));
+  const int npb = (pbn + sh.pbw - 1) / sh.pbw;
+  const int nimg_b = std::min(2 * pbn, nimg_w - 2 * p0);  // images in this batch
+  const int bpi = (p->n_cells + kCellThreads - 1) / kCellThreads;
+  const int groups = (nimg_b + 7) / 8;
+  RF_TIMED(tm, RF_K_GRID,
+           (k_cellsum<<<(unsigned)(groups * 8 * bpi), kCellThreads, 0, s>>>(
+               vi, p->nbl * p->nchan, 2 * p0, nimg_b, p->n_cells, bpi, p->d_ucell_off,
+               p->d_contrib, cv)));
+  RF_TIMED(tm, RF_K_ROWS,
+           (k_rows_pairs<N><<<(unsigned)(npb * p->n_rp), RowPairCfg<N>::NT, 0, s>>>(
+               cv, p->n_cells, nimg_w, p0, pbn, p->d_rp_row, p->d_rp_sa, p->d_rp_sb, p->n_rp,
+               p->n_rows, p->d_zs_off, p->d_zs_u, p->d_zs_ck, p->d_zs_cmk, p->d_tw, M,
+               epart)));
+  const float inv_w = 1.0f / (float)p->W;
+  RF_TIMED(tm, RF_K_COLS,
+           (k_cols_stats<N><<<(unsigned)(pbn * sh.cbp), ColCfg<N>::NT, 0, s>>>(
+               M, p->n_rows, p->d_row_slot, nimg_w, p0, pbn, inv_w, p->d_tw, epart, p->n_rp,
+               part, list, sh.reg)));
+  hipStream_t ss = s;
+  if (ov) {
+    RF_HIP_TRY(hipEventRecord(ov->cols_done[db], s));
+    RF_HIP_TRY(hipStreamWaitEvent(ov->side, ov->cols_done[db], 0));
+    ss = ov->side;
+  }
+  RF_TIMED(tm, RF_K_SELECT,
+           (k_select<<<(unsigned)(2 * pbn), kSelThreads, 0, ss>>>(
+               part, list, sh.cbp, sh.reg, nimg_w, p0, pbn, N, dm_idx, width_idx, width,
+               stat_base, stats, cand, cap, ncand, fb, fb + 1, p->threshold, p->t_begin,
+               p->t_end)));
+  if (ov) {
+    RF_HIP_TRY(hipEventRecord(ov->sel_done[db], ov->side));
+    ov->used[db] = true;
+  }
+  return RF_OK;
+}
+
+rf_status batch(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_w, int p0, int pbn,
+                int dm_idx, int width_idx, int width, int64_t stat_base, char *ws,
+                const Layout &L, int db, rf_image_stats *stats, rf_candidate *cand, int cap,
+                int32_t *ncand, hipStream_t s, Timer *tm, Overlap *ov) {
+#define RF_BATCH(NN)                                                                            \
+  return batch_n<NN>(p, sh, vi, nimg_w, p0, pbn, dm_idx, width_idx, width, stat_base, ws, L, \
+                     db, stats, cand, cap, ncand, s, tm, ov)
+  switch (p->npix) {
+    case 64: RF_BATCH(64);
+    case 128: RF_BATCH(128);
+    case 256: RF_BATCH(256);
+    case 512: RF_BATCH(512);
+    case 1024: RF_BATCH(1024);
+    default: RF_BATCH(2048);
+  }
+#undef RF_BATCH
+}
+
+int lcm_int(int a, int b) { return a / std::gcd(a, b) * b; }
+
+}  // namespace
+
+namespace {
+rf_status drs_timed(const rf_plan *p, const int32_t *d_delay_row, const void *vis,
+                    const int *widths, int nw, float2 *const *vi_out, hipStream_t s, Timer *tm) {
+  const int nbc = p->nbl * p->nchan;
+  // process the widths in groups of kMaxW whose least common multiple keeps a
+  // time chunk short; each group reads the segment once
+  int j = 0;
+  while (j < nw) {
+    WidthSet ws{};
+    int L = 1, n = 0;
+    while (j + n < nw && n < kMaxW) {
+      const int L2 = lcm_int(L, widths[j + n]);
+      if (n > 0 && L2 > 256) break;
+      L = L2;
+      ws.w[n] = widths[j + n];
+      ws.nk[n] = p->nint / widths[j + n];
+      ws.out[n] = vi_out[j + n];
+      ++n;
+    }
+    ws.nw = n;
+    const int tchunk = L * std::max(1, 64 / L);
+    dim3 grid((nbc + kDrsThreads - 1) / kDrsThreads, (p->nint + tchunk - 1) / tchunk);
+    RF_HIP_TRY(tm->mark(RF_K_DRS));
+    if (p->vis_dtype == RF_CF32) {
+      if (p->npol == 2)
+        k_drs<float2, 2><<<grid, kDrsThreads, 0, s>>>((const float2 *)vis, d_delay_row, p->nint,
+                                                      nbc, p->nchan, tchunk, ws);
+      else
+        k_drs<float2, 1><<<grid, kDrsThreads, 0, s>>>((const float2 *)vis, d_delay_row, p->nint,
+                                                      nbc, p->nchan, tchunk, ws);
+    } else {
+      if (p->npol == 2)
+        k_drs<__half2, 2><<<grid, kDrsThreads, 0, s>>>((const __half2 *)vis, d_delay_row,
+                                                       p->nint, nbc, p->nchan, tchunk, ws);
+      else
+        k_drs<__half2, 1><<<grid, kDrsThreads, 0, s>>>((const __half2 *)vis, d_delay_row,
+                                                       p->nint, nbc, p->nchan, tchunk, ws);
+    }
+    RF_HIP_TRY(hipGetLastError());
+    RF_HIP_TRY(tm->mark(-1));
+    j += n;
+  }
+  return RF_OK;
+}
+}  // namespace
+
+rf_status launch_drs(const rf_plan *p, const int32_t *d_delay_row, const void *vis,
+                     const int *widths, int nw, float2 *const *vi_out, hipStream_t s) {
+  Timer none;
+  return drs_timed(p, d_delay_row, vis, widths, nw, vi_out, s, &none);
+}
+
+size_t segment_ws_bytes(const rf_plan *p) {
+  if (p->W == 0 || p->n_rows == 0) return std::max(layout_of(p).total, steps_ws_bytes(p));
+  return layout_of(p).total;
+}
+
+rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
+                      int32_t *ncand, rf_image_stats *stats, void *ws_v, size_t ws_bytes,
+                      hipStream_t s, rf_kernel_times *kt) {
+  Timer timer;
+  timer.kt = kt;
+  timer.s = s;
+  Timer *tm = &timer;
+  char *ws = static_cast<char *>(ws_v);
+  const Layout L = layout_of(p);
+  const Shape sh = shape_of(p);
+  const size_t nbc = (size_t)p->nbl * p->nchan;
+  int32_t *fb = (int32_t *)(ws + L.fb);
+  rf_status st = launch_zero_i32(ncand, 1, s);
+  if (st != RF_OK) return st;
+  st = launch_zero_i32(fb, 1, s);
+  if (st != RF_OK) return st;
+  if (p->W == 0 || p->n_rows == 0) {
+    // nothing is gridded: every image is identically zero; the step chain
+    // produces the (zero) statistics
+    return run_segment_steps(p, vis, cand, cap, ncand, stats, ws, ws_bytes, s);
+  }
+  Overlap overlap;
+  Overlap *ov = nullptr;
+  if (!kt) {
+    RF_HIP_TRY(overlap.init());
+    ov = &overlap;
+  }
+  int nbatch = 0;
+  float2 *vi = (float2 *)(ws + L.vi);
+  std::vector<float2 *> vi_out(p->nwidth);
+  for (int j = 0; j < p->nwidth; ++j) vi_out[j] = vi + L.vi_off[j];
+  for (int i = 0; i < p->ndm; ++i) {
+    st = drs_timed(p, p->d_delay + (size_t)i * p->nchan, vis, p->width.data(), p->nwidth,
+                   vi_out.data(), s, tm);
+    if (st != RF_OK) return st;
+    for (int j = 0; j < p->nwidth; ++j) {
+      const int w = p->width[j];
+      const int nimg_w = p->nint / w;
+      const int npairs = (nimg_w + 1) / 2;
+      const int64_t base = p->img_base[(size_t)i * p->nwidth + j];
+      for (int p0 = 0; p0 < npairs; p0 += sh.pb) {
+        const int pbn = std::min(sh.pb, npairs - p0);
+        st = batch(p, sh, vi_out[j], nimg_w, p0, pbn, i, j, w, base, ws, L, nbatch & 1, stats,
+                   cand, cap, ncand, s, tm, ov);
+        if (st != RF_OK) return st;
+        ++nbatch;
+      }
+    }
+    RF_HIP_TRY(tm->flush());
+  }
+  if (ov) {  // join: the caller's stream waits for the last selects
+    for (int d = 0; d < 2; ++d)
+      if (ov->used[d]) RF_HIP_TRY(hipStreamWaitEvent(s, ov->sel_done[d], 0));
+  }
+  // exact fallback for the images whose median left the bracket
+  int32_t nfb = 0;
+  RF_HIP_TRY(hipMemcpyAsync(&nfb, fb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  RF_HIP_TRY(hipStreamSynchronize(s));
+  if (nfb == 0) return RF_OK;
+  std::vector<int32_t> idx(nfb);
+  RF_HIP_TRY(hipMemcpyAsync(idx.data(), fb + 1, sizeof(int32_t) * nfb, hipMemcpyDeviceToHost, s));
+  RF_HIP_TRY(hipStreamSynchronize(s));
+  std::sort(idx.begin(), idx.end());
+  void *dd = ws + L.dd;
+  float2 *rs = (float2 *)(ws + L.rs);
+  float2 *grid = (float2 *)(ws + L.grid);
+  float *img = (float *)(ws + L.img);
+  float2 *mws = (float2 *)(ws + L.mws);
+  const size_t per_int = nbc * p->npol;
+  int cur_i = -1, cur_j = -1;
+  for (int32_t g : idx) {
+    // image index -> (dm, width, k)
+    int i = 0, j = 0;
+    for (i = p->ndm - 1; i > 0 && p->img_base[(size_t)i * p->nwidth] > g; --i) {
+    }
+    for (j = p->nwidth - 1; j > 0 && p->img_base[(size_t)i * p->nwidth + j] > g; --j) {
+    }
+    const int k = (int)(g - p->img_base[(size_t)i * p->nwidth + j]);
+    const int w = p->width[j];
+    if (i != cur_i) {
+      st = launch_dedisperse(p, p->d_delay + (size_t)i * p->nchan, vis, dd, s);
+      if (st != RF_OK) return st;
+      cur_i = i;
+      cur_j = -1;
+    }
+    if (j != cur_j) {
+      st = launch_resample(p, w, dd, p->vis_dtype, p->nint, rs, s);
+      if (st != RF_OK) return st;
+      cur_j = j;
+    }
+    RF_HIP_TRY(tm->mark(RF_K_FALLBACK));
+    // image the pair the fused path used (2m, 2m+1): two real images share a
+    // complex transform, so the partner is needed for identical rounding
+    const int k0 = k & ~1;
+    const int npair = std::min(2, p->nint / w - k0);
+    st = launch_grid_dense(p, rs + (size_t)k0 * per_int, npair, grid, s);
+    if (st != RF_OK) return st;
+    st = launch_image_dense(p, grid, npair, img, mws, s);
+    if (st != RF_OK) return st;
+    const rf_tag_gen gen{i, j, w, k};
+    st = launch_search(p, img + (size_t)(k - k0) * p->npix * p->npix, 1, nullptr, &gen,
+                       stats ? stats + g : nullptr, cand, cap, ncand, s);
+    if (st != RF_OK) return st;
+    RF_HIP_TRY(tm->mark(-1));
+  }
+  RF_HIP_TRY(tm->flush());
+  return RF_OK;
+}

@@ -22,8 +22,9 @@ template <int N>
 __global__ __launch_bounds__(RowCfg<N>::NT) void k_rows_dense(
     const float2 *__restrict__ grid, int nimg, const int32_t *__restrict__ rows, int n_rows,
     int row_blocks, const float2 *__restrict__ tw_g, float2 *__restrict__ M) {
-  constexpr int F = RowCfg<N>::F, NT = RowCfg<N>::NT;
-  __shared__ float2 buf[F * N];
+  constexpr int F = RowCfg<N>::F, NT = RowCfg<N>::NT, S = RowCfg<N>::STRIDE;
+  constexpr int PS = FftShape<N>::PS;
+  __shared__ float2 buf[F * S];
   __shared__ float2 tw[N];
   const int pair = blockIdx.x / row_blocks;
   const int slot0 = (blockIdx.x % row_blocks) * F;
@@ -47,19 +48,16 @@ __global__ __launch_bounds__(RowCfg<N>::NT) void k_rows_dense(
         b = Gb[(size_t)r * N + u];
         bm = Gb[(size_t)rm * N + um];
       }
-      const float px = a.x + am.x, py = a.y - am.y;   // G_a[k] + conj G_a[-k]
-      const float qx = b.x + bm.x, qy = b.y - bm.y;   // G_b[k] + conj G_b[-k]
-      const float sg = ((r + u) & 1) ? -0.5f : 0.5f;  // (-1)^(u+v) / 2
-      z = make_float2(sg * (px - qy), sg * (py + qx));
+      z = zval(a, am, b, bm, ((r + u) & 1) ? -0.5f : 0.5f);
     }
-    buf[f * N + u] = z;
+    buf[f * S + pidx<PS>(u)] = z;
   }
   __syncthreads();
-  fft_inverse<N, F, NT, N>(buf, tw, tid);
+  fft_inverse<N, F, NT, S>(buf, tw, tid);
   for (int e = tid; e < F * N; e += NT) {
     const int f = e / N, x = e % N;
     const int slot = slot0 + f;
-    if (slot < n_rows) M[((size_t)pair * n_rows + slot) * N + x] = buf[f * N + x];
+    if (slot < n_rows) M[((size_t)pair * n_rows + slot) * N + x] = buf[f * S + pidx<PS>(x)];
   }
 }
 
@@ -68,6 +66,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_image(
     const float2 *__restrict__ M, int n_rows, const int32_t *__restrict__ row_slot, int nimg,
     float inv_w, const float2 *__restrict__ tw_g, float *__restrict__ img) {
   constexpr int COLS = ColCfg<N>::COLS, NT = ColCfg<N>::NT, S = ColCfg<N>::STRIDE;
+  constexpr int PS = FftShape<N>::PS;
   constexpr int CB = N / COLS;
   __shared__ float2 buf[COLS * S];
   __shared__ float2 tw[N];
@@ -79,7 +78,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_image(
   for (int e = tid; e < N * COLS; e += NT) {
     const int r = e / COLS, x = e % COLS;
     const int slot = row_slot[r];
-    buf[x * S + r] = slot >= 0 ? Mp[(size_t)slot * N + x] : make_float2(0.f, 0.f);
+    buf[x * S + pidx<PS>(r)] = slot >= 0 ? Mp[(size_t)slot * N + x] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   fft_inverse<N, COLS, NT, S>(buf, tw, tid);
@@ -88,7 +87,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_image(
   const bool hasb = 2 * pair + 1 < nimg;
   for (int e = tid; e < N * COLS; e += NT) {
     const int y = e / COLS, x = e % COLS;
-    const float2 v = buf[x * S + y];
+    const float2 v = buf[x * S + pidx<PS>(y)];
     ia[(size_t)y * N + x] = v.x * inv_w;
     if (hasb) ib[(size_t)y * N + x] = v.y * inv_w;
   }

@@ -22,7 +22,8 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 bool finite(double x) { return std::isfinite(x); }
 
 struct TableLayout {
-  size_t freq, uvw, dm, delay, cells, contrib, ucell, ucell_off, rows, row_slot, tw, total;
+  size_t freq, uvw, dm, delay, cells, contrib, ucell, ucell_off, rows, row_slot, tw;
+  size_t rp_row, rp_sa, rp_sb, zs_off, zs_u, zs_ck, zs_cmk, total;
 };
 
 TableLayout table_layout(const rf_plan_desc *d) {
@@ -45,6 +46,13 @@ TableLayout table_layout(const rf_plan_desc *d) {
   L.rows = take(sizeof(int32_t) * d->npix);
   L.row_slot = take(sizeof(int32_t) * d->npix);
   L.tw = take(sizeof(float2) * d->npix);
+  L.rp_row = take(sizeof(int32_t) * d->npix);
+  L.rp_sa = take(sizeof(int32_t) * d->npix);
+  L.rp_sb = take(sizeof(int32_t) * d->npix);
+  L.zs_off = take(sizeof(int32_t) * (d->npix + 1));
+  L.zs_u = take(sizeof(int32_t) * 2 * bc);
+  L.zs_ck = take(sizeof(int32_t) * 2 * bc);
+  L.zs_cmk = take(sizeof(int32_t) * 2 * bc);
   L.total = o;
   return L;
 }
@@ -155,6 +163,13 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
   p->d_rows = (int32_t *)(base + L.rows);
   p->d_row_slot = (int32_t *)(base + L.row_slot);
   p->d_tw = (float2 *)(base + L.tw);
+  p->d_rp_row = (int32_t *)(base + L.rp_row);
+  p->d_rp_sa = (int32_t *)(base + L.rp_sa);
+  p->d_rp_sb = (int32_t *)(base + L.rp_sb);
+  p->d_zs_off = (int32_t *)(base + L.zs_off);
+  p->d_zs_u = (int32_t *)(base + L.zs_u);
+  p->d_zs_ck = (int32_t *)(base + L.zs_ck);
+  p->d_zs_cmk = (int32_t *)(base + L.zs_cmk);
 
   RF_HIP_TRY(hipMemcpyAsync(d_freq, p->freq.data(), sizeof(double) * d->nchan,
                             hipMemcpyHostToDevice, s));
@@ -209,6 +224,42 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
   std::vector<float2> tw(N);
   for (int m = 0; m < N; ++m) tw[m] = unit_root(m, N);
 
+  // Z positions per row pair {v, -v}: the union of row v's own cells and the
+  // mirrors of row -v's cells, each with both cell indices.
+  std::vector<int32_t> row_begin(N + 1, 0);
+  for (int32_t c = 0; c < p->n_cells; ++c) row_begin[ucell[c] / N + 1]++;
+  for (int r = 0; r < N; ++r) row_begin[r + 1] += row_begin[r];
+  std::vector<int32_t> rp_row, rp_sa, rp_sb, zs_off, zs_u, zs_ck, zs_cmk;
+  zs_off.push_back(0);
+  std::vector<std::pair<int32_t, std::pair<int32_t, int32_t>>> tmp;
+  for (size_t sidx = 0; sidx < rows.size(); ++sidx) {
+    const int r = rows[sidx], rm = (N - r) & (N - 1);
+    if (r > N / 2) continue;  // the pair is handled from its lower row
+    rp_row.push_back(r);
+    rp_sa.push_back((int32_t)sidx);
+    rp_sb.push_back(row_slot[rm]);
+    tmp.clear();
+    for (int32_t c = row_begin[r]; c < row_begin[r + 1]; ++c)
+      tmp.push_back({ucell[c] % N, {c, -1}});
+    for (int32_t c = row_begin[rm]; c < row_begin[rm + 1]; ++c)
+      tmp.push_back({(N - ucell[c] % N) & (N - 1), {-1, c}});
+    std::sort(tmp.begin(), tmp.end());
+    for (size_t q = 0; q < tmp.size();) {
+      int32_t u = tmp[q].first, ck = -1, cmk = -1;
+      while (q < tmp.size() && tmp[q].first == u) {
+        if (tmp[q].second.first >= 0) ck = tmp[q].second.first;
+        if (tmp[q].second.second >= 0) cmk = tmp[q].second.second;
+        ++q;
+      }
+      zs_u.push_back(u);
+      zs_ck.push_back(ck);
+      zs_cmk.push_back(cmk);
+    }
+    zs_off.push_back((int32_t)zs_u.size());
+  }
+  p->n_rp = (int32_t)rp_row.size();
+  p->n_zs = (int32_t)zs_u.size();
+
   if (!contrib.empty())
     RF_HIP_TRY(hipMemcpyAsync(p->d_contrib, contrib.data(), sizeof(int32_t) * contrib.size(),
                               hipMemcpyHostToDevice, s));
@@ -223,6 +274,20 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
   RF_HIP_TRY(hipMemcpyAsync(p->d_row_slot, row_slot.data(), sizeof(int32_t) * N,
                             hipMemcpyHostToDevice, s));
   RF_HIP_TRY(hipMemcpyAsync(p->d_tw, tw.data(), sizeof(float2) * N, hipMemcpyHostToDevice, s));
+  RF_HIP_TRY(hipMemcpyAsync(p->d_zs_off, zs_off.data(), sizeof(int32_t) * zs_off.size(),
+                            hipMemcpyHostToDevice, s));
+  if (p->n_rp > 0) {
+    const size_t rb = sizeof(int32_t) * p->n_rp;
+    RF_HIP_TRY(hipMemcpyAsync(p->d_rp_row, rp_row.data(), rb, hipMemcpyHostToDevice, s));
+    RF_HIP_TRY(hipMemcpyAsync(p->d_rp_sa, rp_sa.data(), rb, hipMemcpyHostToDevice, s));
+    RF_HIP_TRY(hipMemcpyAsync(p->d_rp_sb, rp_sb.data(), rb, hipMemcpyHostToDevice, s));
+  }
+  if (p->n_zs > 0) {
+    const size_t zb = sizeof(int32_t) * p->n_zs;
+    RF_HIP_TRY(hipMemcpyAsync(p->d_zs_u, zs_u.data(), zb, hipMemcpyHostToDevice, s));
+    RF_HIP_TRY(hipMemcpyAsync(p->d_zs_ck, zs_ck.data(), zb, hipMemcpyHostToDevice, s));
+    RF_HIP_TRY(hipMemcpyAsync(p->d_zs_cmk, zs_cmk.data(), zb, hipMemcpyHostToDevice, s));
+  }
   RF_HIP_TRY(hipStreamSynchronize(s));
 
   p->max_delay = p->h_delay.empty() ? 0 : *std::max_element(p->h_delay.begin(), p->h_delay.end());
@@ -332,6 +397,9 @@ rf_status rf_workspace_bytes(const rf_plan *p, int32_t op, int64_t nimg, size_t 
     case RF_OP_SEGMENT:
       *bytes = segment_ws_bytes(p);
       return RF_OK;
+    case RF_OP_SEGMENT_STEPS:
+      *bytes = steps_ws_bytes(p);
+      return RF_OK;
     default:
       return RF_EINVAL;
   }
@@ -404,7 +472,35 @@ rf_status rf_search_segment(const rf_plan *p, const void *d_vis, rf_candidate *d
   if (ws_bytes < need) return RF_EWORKSPACE;
   if (!d_ws) return RF_EINVAL;
   return run_segment(p, d_vis, d_cand, cap, d_ncand, d_stats, d_ws, ws_bytes,
-                     (hipStream_t)stream);
+                     (hipStream_t)stream, nullptr);
+}
+
+rf_status rf_search_segment_profile(const rf_plan *p, const void *d_vis, rf_candidate *d_cand,
+                                    int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,
+                                    void *d_ws, size_t ws_bytes, void *stream,
+                                    rf_kernel_times *times) {
+  if (!p || !times) return RF_EINVAL;
+  if (cap < 0) return RF_ERANGE;
+  if (!d_vis || !d_ncand || (cap > 0 && !d_cand)) return RF_EINVAL;
+  const size_t need = segment_ws_bytes(p);
+  if (ws_bytes < need) return RF_EWORKSPACE;
+  if (!d_ws) return RF_EINVAL;
+  std::memset(times, 0, sizeof(*times));
+  return run_segment(p, d_vis, d_cand, cap, d_ncand, d_stats, d_ws, ws_bytes,
+                     (hipStream_t)stream, times);
+}
+
+rf_status rf_search_segment_steps(const rf_plan *p, const void *d_vis, rf_candidate *d_cand,
+                                  int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,
+                                  void *d_ws, size_t ws_bytes, void *stream) {
+  if (!p) return RF_EINVAL;
+  if (cap < 0) return RF_ERANGE;
+  if (!d_vis || !d_ncand || (cap > 0 && !d_cand)) return RF_EINVAL;
+  const size_t need = steps_ws_bytes(p);
+  if (ws_bytes < need) return RF_EWORKSPACE;
+  if (!d_ws) return RF_EINVAL;
+  return run_segment_steps(p, d_vis, d_cand, cap, d_ncand, d_stats, d_ws, ws_bytes,
+                           (hipStream_t)stream);
 }
 
 }  // extern "C"

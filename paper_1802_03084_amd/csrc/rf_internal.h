@@ -38,6 +38,20 @@ struct rf_plan {
   int32_t *d_rows;          // [n_rows] occupied rows, ascending
   int32_t *d_row_slot;      // [N] compact slot of a row in d_rows, or -1
   float2 *d_tw;             // [N] exp(+2 pi i m / N)
+  // Z positions of the paired Hermitian transform, grouped by row pair
+  // {v, -v} (v in [0, N/2], occupied): row pair rp has rows v = rp_row[rp]
+  // (compact slot rp_sa[rp]) and -v (slot rp_sb[rp]); its positions
+  // zs_off[rp] .. zs_off[rp+1] are columns zs_u of row v with zs_ck the cell
+  // index (into d_ucell) at (v, u) and zs_cmk the one at (-v, -u), -1 where
+  // the grid is empty.  Row -v's positions are the mirrors (-u).
+  int32_t n_rp, n_zs;
+  int32_t *d_rp_row;        // [n_rp]
+  int32_t *d_rp_sa;         // [n_rp]
+  int32_t *d_rp_sb;         // [n_rp]
+  int32_t *d_zs_off;        // [n_rp + 1]
+  int32_t *d_zs_u;          // [n_zs]
+  int32_t *d_zs_ck;         // [n_zs]
+  int32_t *d_zs_cmk;        // [n_zs]
 
   // host copies used by rf_get_* and the launchers
   std::vector<int32_t> h_delay;
@@ -83,8 +97,12 @@ rf_status launch_search(const rf_plan *p, const float *img, int nimg, const rf_i
 rf_status launch_zero_i32(int32_t *p, int n, hipStream_t s);
 rf_status launch_zero_f32(float *p, size_t nfloat, hipStream_t s);
 
-// whole segment
+// whole segment: fused path (k_fused.hip) and the step chain (rf_segment.cpp)
 size_t segment_ws_bytes(const rf_plan *p);
+size_t steps_ws_bytes(const rf_plan *p);
+rf_status run_segment_steps(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
+                            int32_t *ncand, rf_image_stats *stats, void *ws, size_t ws_bytes,
+                            hipStream_t s);
 rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
                       int32_t *ncand, rf_image_stats *stats, void *ws, size_t ws_bytes,
-                      hipStream_t s);
+                      hipStream_t s, rf_kernel_times *kt);

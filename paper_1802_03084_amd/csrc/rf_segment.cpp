@@ -1,7 +1,8 @@
-// Whole-segment search: the loop of Law et al. 2018, Figure 2 (DM trials
-// outside, sampling times inside, every resampled integration imaged and
-// thresholded), driven from the host as a chain of the step kernels on one
-// stream.  Intermediates live in the caller's workspace.
+// Whole-segment search as a chain of the step kernels: the loop of Law et al.
+// 2018, Figure 2 (DM trials outside, sampling times inside, every resampled
+// integration imaged and thresholded), driven from the host on one stream
+// with dense intermediates in the caller's workspace.  This is the plain
+// reference path; the fused path in k_fused.hip gives the same results.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,11 +43,11 @@ SegLayout seg_layout(const rf_plan *p) {
 
 }  // namespace
 
-size_t segment_ws_bytes(const rf_plan *p) { return seg_layout(p).total; }
+size_t steps_ws_bytes(const rf_plan *p) { return seg_layout(p).total; }
 
-rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
-                      int32_t *ncand, rf_image_stats *stats, void *ws, size_t ws_bytes,
-                      hipStream_t s) {
+rf_status run_segment_steps(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
+                            int32_t *ncand, rf_image_stats *stats, void *ws, size_t ws_bytes,
+                            hipStream_t s) {
   (void)ws_bytes;
   const SegLayout L = seg_layout(p);
   char *base = static_cast<char *>(ws);

@@ -198,3 +198,43 @@ def test_segment_window_and_capacity(torch):
     g2 = gpu_plan(p2)
     rows, n, _ = g2.search_segment(vis, cap=7)
     assert n == p2.n_images() and len(rows) == 7
+
+
+@pytest.mark.parametrize("name", ["tiny", "small", "small_n64_p1", "small_n512"])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_fused_equals_steps(torch, name, dtype):
+    """rf_search_segment (fused) and rf_search_segment_steps (plain chain)
+    give bit-identical statistics and candidates."""
+    p = PRESETS[name]()
+    say("fused vs steps", name, dtype)
+    g = gpu_plan(p, vis_dtype=dtype)
+    dv = upload(p.make_vis(), dtype)
+    r1, n1, s1 = g.search_segment(dv, cap=4096, with_stats=True)
+    r2, n2, s2 = g.search_segment(dv, cap=4096, with_stats=True, steps=True)
+    assert n1 == n2
+    assert np.array_equal(r1, r2)
+    assert np.array_equal(s1.view(np.int32), s2.view(np.int32))
+
+
+def test_fused_bright_source_exact_fallback(torch):
+    """A very bright pulse moves the image rms far from the noise median, so
+    the median bracket misses and the exact recomputation must take over."""
+    p = rfgen.tiny()
+    p.pulses = [rfgen.Pulse(dm_idx=1, width_idx=0, t0=3, x=140, y=120, snr=400.0)]
+    say("bright source fallback")
+    g = gpu_plan(p)
+    o = oracle_plan(p)
+    vis = p.make_vis()
+    dv = upload(vis)
+    r1, n1, s1 = g.search_segment(dv, cap=4096, with_stats=True)
+    r2, n2, s2 = g.search_segment(dv, cap=4096, with_stats=True, steps=True)
+    assert np.array_equal(s1.view(np.int32), s2.view(np.int32))
+    assert np.array_equal(r1, r2)
+    key = (1, 0, 3)
+    st, _, im = oracle.search(vis, o, select={key}, keep_images=True)
+    ref = st[key]
+    s = s1[g.image_base(1, 0) + 3]
+    assert (int(s["x"]), int(s["y"])) == (140, 120)
+    amax = float(np.max(np.abs(im[key])))
+    assert abs(s["sigma"] - ref[3]) <= 1.4826 * TOL32 * amax
+    assert s["snr"] > 50
