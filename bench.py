@@ -94,6 +94,10 @@ def main():
     ap.add_argument("--cpu-images", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain step-chain comparison")
+    ap.add_argument("--dms", type=int, default=0,
+                    help="search only the first K DM trials (short runs for hardware counters)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run only the event-timed kernel pass (for counter collection)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -106,6 +110,9 @@ def main():
     import rfgen
 
     p = rfgen.survey() if args.workload == "survey" else rfgen.tiny()
+    if args.dms > 0:
+        p.dms = p.dms[: args.dms]
+        p.pulses = [q for q in p.pulses if q.dm_idx < args.dms]
     t = time.perf_counter()
     vis = p.make_vis()
     log(f"generated {p.name} segment {vis.shape} {vis.nbytes / 1e9:.2f} GB in {time.perf_counter() - t:.1f}s")
@@ -138,6 +145,10 @@ def main():
         f"rows={plan.info['n_rows']}, workspace {ws.numel() / 1e9:.2f} GB")
 
     cap = 65536
+    if args.profile_only:
+        times, _, n = plan.profile_segment(dvis, cap=cap, ws=ws)
+        log("profile pass: " + ", ".join(f"{k}={v[0]:.1f} ms/{v[1]}" for k, v in times.items() if v[1]))
+        return
     for w in range(args.warmup):
         t = time.perf_counter()
         rows, n, _ = plan.search_segment(dvis, cap=cap, ws=ws)

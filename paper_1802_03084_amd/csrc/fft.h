@@ -207,4 +207,32 @@ struct ColCfg {
   static constexpr int STRIDE = FftShape<N>::PADDED + 1;          // odd: spreads the transpose
 };
 
+// Column tile of the row-transformed data: buf[x][pidx(v)] = M[slot(v)][x0 + x]
+// (zero for rows without samples), COLS columns.  The trip count is a
+// compile-time constant so every thread issues all of its loads before it
+// stores any of them.
+template <int N>
+__device__ __forceinline__ void load_col_tile(const float2 *__restrict__ Mp,
+                                              const int32_t *__restrict__ row_slot, float2 *buf,
+                                              int tid) {
+  constexpr int COLS = ColCfg<N>::COLS, NT = ColCfg<N>::NT, S = ColCfg<N>::STRIDE;
+  constexpr int PS = FftShape<N>::PS;
+  constexpr int Q = (N * COLS + NT - 1) / NT;
+  float2 v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = tid + q * NT;
+    v[q] = make_float2(0.f, 0.f);
+    if ((N * COLS) % NT == 0 || e < N * COLS) {
+      const int slot = row_slot[e / COLS];
+      if (slot >= 0) v[q] = Mp[(size_t)slot * N + e % COLS];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = tid + q * NT;
+    if ((N * COLS) % NT == 0 || e < N * COLS) buf[(e % COLS) * S + pidx<PS>(e / COLS)] = v[q];
+  }
+}
+
 }  // namespace rf

@@ -52,6 +52,7 @@ struct ColPart {   // per (image, column workgroup)
   int32_t maxi;
   uint32_t cnt_lo;
   uint32_t n;      // values inside the bracket (may exceed the region size)
+  float lo, hi;    // the bracket [lo, hi) (identical in every workgroup of a pair)
 };
 
 __device__ __forceinline__ bool better(float v, int i, float bv, int bi) {
@@ -156,23 +157,19 @@ __global__ __launch_bounds__(kCellThreads) void k_cellsum(
   const float2 *v = vi + (size_t)(k0 + il) * nbc;
   float2 acc = make_float2(0.f, 0.f);
   const int e = coff[c + 1];
-  int q = coff[c];
-  for (; q + 4 <= e; q += 4) {  // four independent loads in flight
-    const int b0 = contrib[q], b1 = contrib[q + 1], b2 = contrib[q + 2], b3 = contrib[q + 3];
-    const float2 x0 = v[b0], x1 = v[b1], x2 = v[b2], x3 = v[b3];
-    acc.x += x0.x;
-    acc.y += x0.y;
-    acc.x += x1.x;
-    acc.y += x1.y;
-    acc.x += x2.x;
-    acc.y += x2.y;
-    acc.x += x3.x;
-    acc.y += x3.y;
-  }
-  for (; q < e; ++q) {
-    const float2 x = v[contrib[q]];
-    acc.x += x.x;
-    acc.y += x.y;
+  for (int q = coff[c]; q < e; q += 4) {  // four independent loads in flight
+    int b[4];
+    float2 x[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[i] = q + i < e ? contrib[q + i] : -1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = b[i] >= 0 ? v[b[i]] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (b[i] >= 0) {
+        acc.x += x[i].x;
+        acc.y += x[i].y;
+      }
   }
   cv[(size_t)il * n_cells + c] = acc;
 }
@@ -296,12 +293,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
       s_n[tid] = 0;
     }
   }
-  const float2 *Mp = M + (size_t)pl * n_rows * N + x0;
-  for (int e = tid; e < N * COLS; e += NT) {
-    const int r = e / COLS, x = e % COLS;
-    const int slot = row_slot[r];
-    buf[x * S + pidx<PS>(r)] = slot >= 0 ? Mp[(size_t)slot * N + x] : make_float2(0.f, 0.f);
-  }
+  load_col_tile<N>(M + (size_t)pl * n_rows * N + x0, row_slot, buf, tid);
   __syncthreads();
   fft_inverse<N, COLS, NT, S>(buf, tw, tid);
   const bool hasb = 2 * (p0 + pl) + 1 < nimg_w;
@@ -385,12 +377,15 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
     cp.maxi = i;
     cp.cnt_lo = c;
     cp.n = s_n[tid];
+    cp.lo = s_br[2 * tid + 0];
+    cp.hi = s_br[2 * tid + 1];
     part[(size_t)(2 * pl + tid) * CB + cb] = cp;
   }
 }
 
 // ------------------------------------------------------------------ select
 constexpr int kBins = 2048;
+constexpr uint32_t kBinCap = 1024;  // values of one bracket bin ranked directly
 
 __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t *wsum) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -449,6 +444,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
   __shared__ int32_t s_i;
   __shared__ uint32_t s_lo, s_n;
   __shared__ int s_ovf;
+  __shared__ float binv[kBinCap];
+  __shared__ uint32_t s_nc;
+  __shared__ float s_med;
   const int il = blockIdx.x;
   const int pl = il >> 1;
   const int k = 2 * (p0 + pl) + (il & 1);
@@ -516,32 +514,80 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
   } else if (!s_ovf && s_lo <= rank && rank < s_lo + s_n) {
     uint32_t r = rank - s_lo;
     const float *lp = list + (size_t)il * cbn * reg;
-    uint32_t prefix = 0;
-    // three radix passes over the kept values: bits 30..20, 19..9, 8..0
-    for (int pass = 0; pass < 3; ++pass) {
-      for (int i = tid; i < kBins; i += kSelThreads) hist[i] = 0;
-      __syncthreads();
-      for (int g = 0; g < cbn; ++g) {
-        const uint32_t ng = cnt[g];
-        for (uint32_t e = tid; e < ng; e += kSelThreads) {
-          const uint32_t key = __float_as_uint(lp[(size_t)g * reg + e]);
-          if (pass == 0) {
-            atomicAdd(&hist[key >> 20], 1u);
-          } else if (pass == 1) {
-            if ((key >> 20) == prefix) atomicAdd(&hist[(key >> 9) & 2047u], 1u);
-          } else {
-            if ((key >> 9) == prefix) atomicAdd(&hist[key & 511u], 1u);
-          }
+    // pass 1: 2048 equal-width bins over the bracket [lo, hi); the bin index
+    // is a monotone function of the value, so the bin holding rank r holds
+    // the wanted order statistic
+    const float lo = pp[0].lo, hi = pp[0].hi;
+    const float scale = (float)kBins / (hi - lo);
+    for (int i = tid; i < kBins; i += kSelThreads) hist[i] = 0;
+    if (tid == 0) s_nc = 0;
+    __syncthreads();
+    for (int g = 0; g < cbn; ++g) {
+      const uint32_t ng = cnt[g];
+      for (uint32_t e = tid; e < ng; e += kSelThreads) {
+        const float v = lp[(size_t)g * reg + e];
+        atomicAdd(&hist[min(kBins - 1, (int)((v - lo) * scale))], 1u);
+      }
+    }
+    __syncthreads();
+    sel_bin(hist, r, wsum, sel);
+    const int b1 = (int)sel[0];
+    const uint32_t r1 = sel[1];
+    __syncthreads();
+    // pass 2: gather that bin's values and rank them directly
+    for (int g = 0; g < cbn; ++g) {
+      const uint32_t ng = cnt[g];
+      for (uint32_t e = tid; e < ng; e += kSelThreads) {
+        const float v = lp[(size_t)g * reg + e];
+        if (min(kBins - 1, (int)((v - lo) * scale)) == b1) {
+          const uint32_t at = atomicAdd(&s_nc, 1u);
+          if (at < kBinCap) binv[at] = v;
         }
       }
-      __syncthreads();
-      sel_bin(hist, r, wsum, sel);
-      const uint32_t bin = sel[0];
-      r = sel[1];
-      __syncthreads();
-      prefix = pass == 0 ? bin : (pass == 1 ? ((prefix << 11) | bin) : ((prefix << 9) | bin));
     }
-    med = __uint_as_float(prefix);
+    __syncthreads();
+    const uint32_t nc = s_nc;
+    if (nc <= kBinCap) {
+      for (uint32_t t = tid; t < nc; t += kSelThreads) {
+        const float v = binv[t];
+        uint32_t less = 0, leq = 0;
+        for (uint32_t u = 0; u < nc; ++u) {
+          less += binv[u] < v;
+          leq += binv[u] <= v;
+        }
+        if (less <= r1 && r1 < leq) s_med = v;  // equal values write the same value
+      }
+      __syncthreads();
+      med = s_med;
+    } else {
+      // a crowded bin: exact three-pass radix select on the bit patterns
+      // (bits 30..20, 19..9, 8..0)
+      uint32_t prefix = 0;
+      for (int pass = 0; pass < 3; ++pass) {
+        for (int i = tid; i < kBins; i += kSelThreads) hist[i] = 0;
+        __syncthreads();
+        for (int g = 0; g < cbn; ++g) {
+          const uint32_t ng = cnt[g];
+          for (uint32_t e = tid; e < ng; e += kSelThreads) {
+            const uint32_t key = __float_as_uint(lp[(size_t)g * reg + e]);
+            if (pass == 0) {
+              atomicAdd(&hist[key >> 20], 1u);
+            } else if (pass == 1) {
+              if ((key >> 20) == prefix) atomicAdd(&hist[(key >> 9) & 2047u], 1u);
+            } else {
+              if ((key >> 9) == prefix) atomicAdd(&hist[key & 511u], 1u);
+            }
+          }
+        }
+        __syncthreads();
+        sel_bin(hist, r, wsum, sel);
+        const uint32_t bin = sel[0];
+        r = sel[1];
+        __syncthreads();
+        prefix = pass == 0 ? bin : (pass == 1 ? ((prefix << 11) | bin) : ((prefix << 9) | bin));
+      }
+      med = __uint_as_float(prefix);
+    }
   } else {
     if (tid == 0) {
       const int slot = atomicAdd(fb_count, 1);

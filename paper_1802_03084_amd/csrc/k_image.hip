@@ -74,12 +74,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_image(
   const int x0 = (blockIdx.x % CB) * COLS;
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
-  const float2 *Mp = M + (size_t)pair * n_rows * N + x0;
-  for (int e = tid; e < N * COLS; e += NT) {
-    const int r = e / COLS, x = e % COLS;
-    const int slot = row_slot[r];
-    buf[x * S + pidx<PS>(r)] = slot >= 0 ? Mp[(size_t)slot * N + x] : make_float2(0.f, 0.f);
-  }
+  load_col_tile<N>(M + (size_t)pair * n_rows * N + x0, row_slot, buf, tid);
   __syncthreads();
   fft_inverse<N, COLS, NT, S>(buf, tw, tid);
   float *ia = img + (size_t)(2 * pair) * N * N + x0;
