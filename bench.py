@@ -98,6 +98,9 @@ def main():
                     help="search only the first K DM trials (short runs for hardware counters)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the event-timed kernel pass (for counter collection)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device (a plain copy kernel of known size, "
+                         "to scale the HBM byte counters) and report its bandwidth")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -108,6 +111,27 @@ def main():
 
     import numpy as np
     import rfgen
+
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda")
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        dst.copy_(src)
+        t0.record()
+        reps = 5
+        for _ in range(reps):
+            dst.copy_(src)
+        t1.record()
+        t1.synchronize()
+        dt = t0.elapsed_time(t1) / reps * 1e-3
+        print(json.dumps({"copy_bytes": n, "read_plus_write_GBps": round(2 * n / dt / 1e9, 1),
+                          "avg_us": round(dt * 1e6, 1)}), flush=True)
+        return
 
     p = rfgen.survey() if args.workload == "survey" else rfgen.tiny()
     if args.dms > 0:

@@ -1,7 +1,6 @@
-// Workgroup-cooperative inverse FFTs in LDS (Stockham autosort, radix 4/8/16).
+// Workgroup-cooperative inverse FFTs (Stockham autosort, radix 8/16/32).
 //
-// A workgroup transforms F independent length-N sequences held in LDS, each
-// starting STRIDE complex elements after the previous one.  A pass of radix R
+// A workgroup transforms F independent length-N sequences.  A pass of radix R
 // (with NS = product of the earlier radices) performs, for every butterfly j
 // in [0, N/R):
 //   v[r] = x[j + r N/R] * w^(r (j mod NS)),  w = exp(+2 pi i / (NS R))
@@ -9,10 +8,12 @@
 //   y[(j / NS) NS R + (j mod NS) + r NS] = v[r]
 // which is the classical self-sorting Stockham formulation of the radix-R
 // Cooley-Tukey FFT: after the last pass y is the inverse DFT in natural
-// order.  Each thread loads all of its butterflies' inputs into registers
-// before a barrier and writes them after it, so one LDS buffer suffices.
-// Twiddles come from an LDS table tw[m] = exp(+2 pi i m / N) computed on the
-// host in float64.
+// order.  N is split into two passes (three for N = 2048) of radix up to 32
+// held in registers: the first pass reads its inputs from wherever the
+// caller keeps them (global memory for the column transform), the passes
+// exchange through one padded LDS buffer, and the last pass hands its
+// outputs to the caller in registers.  Twiddles come from a global table
+// tw[m] = exp(+2 pi i m / N) computed on the host in float64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,29 +40,49 @@ __device__ __forceinline__ float2 crot(float2 x, float c, float s) {
   return make_float2(__builtin_fmaf(x.x, c, -(x.y * s)), __builtin_fmaf(x.x, s, x.y * c));
 }
 
-// x * exp(+2 pi i e / 16).  e is a compile-time constant at every call site
+// x * exp(+2 pi i e / 32).  e is a compile-time constant at every call site
 // after unrolling, so the switch folds away and trivial rotations cost nothing.
-__device__ __forceinline__ float2 rot16(float2 x, int e) {
+__device__ __forceinline__ float2 rot32(float2 x, int e) {
 #pragma clang fp contract(off)
-  constexpr float c1 = 0.92387953251128675613f;  // cos(pi/8)
-  constexpr float s1 = 0.38268343236508977173f;  // sin(pi/8)
+  constexpr float c1 = 0.98078528040323044913f;  // cos(pi/16)
+  constexpr float s1 = 0.19509032201612826785f;  // sin(pi/16)
+  constexpr float c2 = 0.92387953251128675613f;  // cos(pi/8)
+  constexpr float s2 = 0.38268343236508977173f;  // sin(pi/8)
+  constexpr float c3 = 0.83146961230254523708f;  // cos(3pi/16)
+  constexpr float s3 = 0.55557023301960222474f;  // sin(3pi/16)
   constexpr float h = 0.70710678118654752440f;   // cos(pi/4)
-  switch (e & 15) {
+  switch (e & 31) {
     case 0: return x;
     case 1: return crot(x, c1, s1);
-    case 2: return make_float2(h * (x.x - x.y), h * (x.x + x.y));
-    case 3: return crot(x, s1, c1);
-    case 4: return make_float2(-x.y, x.x);
-    case 5: return crot(x, -s1, c1);
-    case 6: return make_float2(-h * (x.x + x.y), h * (x.x - x.y));
-    case 7: return crot(x, -c1, s1);
-    case 8: return make_float2(-x.x, -x.y);
-    case 9: return crot(x, -c1, -s1);
-    case 10: return make_float2(h * (x.y - x.x), -h * (x.x + x.y));
-    case 11: return crot(x, -s1, -c1);
-    case 12: return make_float2(x.y, -x.x);
-    case 13: return crot(x, s1, -c1);
-    case 14: return make_float2(h * (x.x + x.y), h * (x.y - x.x));
+    case 2: return crot(x, c2, s2);
+    case 3: return crot(x, c3, s3);
+    case 4: return make_float2(h * (x.x - x.y), h * (x.x + x.y));
+    case 5: return crot(x, s3, c3);
+    case 6: return crot(x, s2, c2);
+    case 7: return crot(x, s1, c1);
+    case 8: return make_float2(-x.y, x.x);
+    case 9: return crot(x, -s1, c1);
+    case 10: return crot(x, -s2, c2);
+    case 11: return crot(x, -s3, c3);
+    case 12: return make_float2(-h * (x.x + x.y), h * (x.x - x.y));
+    case 13: return crot(x, -c3, s3);
+    case 14: return crot(x, -c2, s2);
+    case 15: return crot(x, -c1, s1);
+    case 16: return make_float2(-x.x, -x.y);
+    case 17: return crot(x, -c1, -s1);
+    case 18: return crot(x, -c2, -s2);
+    case 19: return crot(x, -c3, -s3);
+    case 20: return make_float2(h * (x.y - x.x), -h * (x.x + x.y));
+    case 21: return crot(x, -s3, -c3);
+    case 22: return crot(x, -s2, -c2);
+    case 23: return crot(x, -s1, -c1);
+    case 24: return make_float2(x.y, -x.x);
+    case 25: return crot(x, s1, -c1);
+    case 26: return crot(x, s2, -c2);
+    case 27: return crot(x, s3, -c3);
+    case 28: return make_float2(h * (x.x + x.y), h * (x.y - x.x));
+    case 29: return crot(x, c3, -s3);
+    case 30: return crot(x, c2, -s2);
     default: return crot(x, c1, -s1);
   }
 }
@@ -76,7 +97,7 @@ __device__ constexpr int bitrev(int i) {
   return r;
 }
 
-// In-register inverse DFT of length R in {2, 4, 8, 16}: bit-reversed
+// In-register inverse DFT of length R in {2, 4, 8, 16, 32}: bit-reversed
 // radix-2 decimation in time, natural-order output.
 template <int R>
 __device__ __forceinline__ void dft(float2 (&v)[R]) {
@@ -90,7 +111,7 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
 #pragma unroll
       for (int k = 0; k < len / 2; ++k) {
         const float2 a = t[i + k];
-        const float2 b = rot16(t[i + k + len / 2], k * (16 / len));
+        const float2 b = rot32(t[i + k + len / 2], k * (32 / len));
         t[i + k] = cadd(a, b);
         t[i + k + len / 2] = csub(a, b);
       }
@@ -100,31 +121,101 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
   for (int i = 0; i < R; ++i) v[i] = t[i];
 }
 
-// Padded LDS index: one spare element after every 2^PS, so that the stride-R
-// writes of the first pass (and the strided column gathers) spread over the
-// LDS banks instead of piling onto one.
+// Padded LDS index: one spare element after every 2^PS (PS = log2 of the
+// first radix), so that the stride-R writes of the first pass spread over
+// the LDS banks instead of piling onto one.
 template <int PS>
 __device__ __forceinline__ int pidx(int i) { return i + (i >> PS); }
 
-template <int N, int R, int NS, int F, int NT, int STRIDE, int PS>
-__device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *tw, int tid) {
-  constexpr int NB = N / R;
-  constexpr int TOT = F * NB;
-  constexpr int Q = (TOT + NT - 1) / NT;
+// Radix schedule (two or three passes) and LDS padding for each N.
+template <int N>
+struct FftShape;
+template <> struct FftShape<64> { static constexpr int R0 = 8, R1 = 8, R2 = 1; };
+template <> struct FftShape<128> { static constexpr int R0 = 16, R1 = 8, R2 = 1; };
+template <> struct FftShape<256> { static constexpr int R0 = 16, R1 = 16, R2 = 1; };
+template <> struct FftShape<512> { static constexpr int R0 = 32, R1 = 16, R2 = 1; };
+template <> struct FftShape<1024> { static constexpr int R0 = 32, R1 = 32, R2 = 1; };
+template <> struct FftShape<2048> { static constexpr int R0 = 32, R1 = 8, R2 = 8; };
+template <int N>
+struct FftPad {
+  static constexpr int PS = FftShape<N>::R0 == 32 ? 5 : (FftShape<N>::R0 == 16 ? 4 : 3);
+  static constexpr int PADDED = N + (N >> PS);   // padded length of one sequence
+};
+
+// Butterfly index -> (sequence f, butterfly j).  JF: j fastest across
+// threads (rows: contiguous along the transform); otherwise f fastest
+// (columns: neighbouring threads hold neighbouring columns).
+template <int F, int NB, bool JF>
+__device__ __forceinline__ void fj_of(int idx, int &f, int &j) {
+  if (JF) {
+    f = idx / NB;
+    j = idx % NB;
+  } else {
+    f = idx % F;
+    j = idx / F;
+  }
+}
+
+// First pass (no twiddles): inputs from load(f, i) (global memory or LDS),
+// radix-R0 DFT, results to LDS at the Stockham position j R0 + r.
+template <int N, int F, int NT, int S, bool JF, class Load>
+__device__ __forceinline__ void fft_first(float2 *buf, int tid, Load load) {
+  constexpr int R = FftShape<N>::R0, NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT;
+  constexpr int PS = FftPad<N>::PS;
   float2 v[Q][R];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int idx = tid + q * NT;
     if ((TOT % NT) == 0 || idx < TOT) {
-      const int f = idx / NB, j = idx % NB;
-      const float2 *src = buf + f * STRIDE;
+      int f, j;
+      fj_of<F, NB, JF>(idx, f, j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = src[pidx<PS>(j + r * NB)];
-      if (NS > 1) {
-        const int jm = j % NS;
+      for (int r = 0; r < R; ++r) v[q][r] = load(f, j + r * NB);
+    }
+  }
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[jm * r * (N / (NS * R))]);
-      }
+  for (int q = 0; q < Q; ++q) dft<R>(v[q]);
+  __syncthreads();  // inputs may have come from buf
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = tid + q * NT;
+    if ((TOT % NT) == 0 || idx < TOT) {
+      int f, j;
+      fj_of<F, NB, JF>(idx, f, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[f * S + pidx<PS>(j * R + r)] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Loads butterfly (f, j) of a radix-R pass from LDS and applies the twiddles
+// w^(r (j mod NS)), w = exp(+2 pi i / (NS R)), from the global table
+// tw[m] = exp(+2 pi i m / N).
+template <int N, int R, int NS, int S, int PS>
+__device__ __forceinline__ void fft_gather(const float2 *buf, const float2 *__restrict__ tw, int f,
+                                           int j, float2 (&v)[R]) {
+  constexpr int NB = N / R;
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = buf[f * S + pidx<PS>(j + r * NB)];
+  const int jm = j % NS;
+#pragma unroll
+  for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[jm * r * (N / (NS * R))]);
+}
+
+// Middle pass: LDS -> LDS in place.
+template <int N, int R, int NS, int F, int NT, int S, bool JF>
+__device__ __forceinline__ void fft_mid(float2 *buf, const float2 *__restrict__ tw, int tid) {
+  constexpr int NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT;
+  constexpr int PS = FftPad<N>::PS;
+  float2 v[Q][R];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = tid + q * NT;
+    if ((TOT % NT) == 0 || idx < TOT) {
+      int f, j;
+      fj_of<F, NB, JF>(idx, f, j);
+      fft_gather<N, R, NS, S, PS>(buf, tw, f, j, v[q]);
       dft<R>(v[q]);
     }
   }
@@ -133,51 +224,87 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *tw, int
   for (int q = 0; q < Q; ++q) {
     const int idx = tid + q * NT;
     if ((TOT % NT) == 0 || idx < TOT) {
-      const int f = idx / NB, j = idx % NB;
-      float2 *dst = buf + f * STRIDE;
+      int f, j;
+      fj_of<F, NB, JF>(idx, f, j);
       const int d0 = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[pidx<PS>(d0 + r * NS)] = v[q][r];
+      for (int r = 0; r < R; ++r) buf[f * S + pidx<PS>(d0 + r * NS)] = v[q][r];
     }
   }
   __syncthreads();
 }
 
-// Radix schedule and LDS padding for each supported N.
-template <int N>
-struct FftShape {
-  static_assert(N >= 64 && N <= 2048 && (N & (N - 1)) == 0, "N must be 2^k in [64, 2048]");
-  static constexpr int PS = (N == 512) ? 3 : 4;  // log2 of the first radix
-  static constexpr int PADDED = N + (N >> PS);   // padded length of one sequence
-};
+// Last pass: LDS -> registers, results handed to store(f, k, value) with k the
+// natural-order output index.
+template <int N, int R, int NS, int F, int NT, int S, bool JF, class Store>
+__device__ __forceinline__ void fft_last(const float2 *buf, const float2 *__restrict__ tw, int tid,
+                                         Store store) {
+  constexpr int NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT;
+  constexpr int PS = FftPad<N>::PS;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = tid + q * NT;
+    if ((TOT % NT) == 0 || idx < TOT) {
+      int f, j;
+      fj_of<F, NB, JF>(idx, f, j);
+      float2 v[R];
+      fft_gather<N, R, NS, S, PS>(buf, tw, f, j, v);
+      dft<R>(v);
+      const int d0 = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+      for (int r = 0; r < R; ++r) store(f, d0 + r * NS, v[r]);
+    }
+  }
+}
 
-// Inverse (exp(+i)) unnormalised FFT of F sequences of length N in LDS, each
-// stored padded (element i at pidx(i)) from buf + f * STRIDE.  Callers
-// synchronise before (inputs written) and may read after return.
-template <int N, int F, int NT, int STRIDE>
-__device__ __forceinline__ void fft_inverse(float2 *buf, const float2 *tw, int tid) {
-  constexpr int PS = FftShape<N>::PS;
-  if constexpr (N == 64) {
-    stockham_pass<N, 16, 1, F, NT, STRIDE, PS>(buf, tw, tid);
-    stockham_pass<N, 4, 16, F, NT, STRIDE, PS>(buf, tw, tid);
-  } else if constexpr (N == 128) {
-    stockham_pass<N, 16, 1, F, NT, STRIDE, PS>(buf, tw, tid);
-    stockham_pass<N, 8, 16, F, NT, STRIDE, PS>(buf, tw, tid);
-  } else if constexpr (N == 256) {
-    stockham_pass<N, 16, 1, F, NT, STRIDE, PS>(buf, tw, tid);
-    stockham_pass<N, 16, 16, F, NT, STRIDE, PS>(buf, tw, tid);
-  } else if constexpr (N == 512) {
-    stockham_pass<N, 8, 1, F, NT, STRIDE, PS>(buf, tw, tid);
-    stockham_pass<N, 8, 8, F, NT, STRIDE, PS>(buf, tw, tid);
-    stockham_pass<N, 8, 64, F, NT, STRIDE, PS>(buf, tw, tid);
-  } else if constexpr (N == 1024) {
-    stockham_pass<N, 16, 1, F, NT, STRIDE, PS>(buf, tw, tid);
-    stockham_pass<N, 16, 16, F, NT, STRIDE, PS>(buf, tw, tid);
-    stockham_pass<N, 4, 256, F, NT, STRIDE, PS>(buf, tw, tid);
+// Last pass variant: consume(f, k0, kstep, v) receives a butterfly's R outputs
+// at natural-order indices k0 + r * kstep in increasing r (kstep = NS).
+template <int N, int R, int NS, int F, int NT, int S, bool JF, class Consume>
+__device__ __forceinline__ void fft_last_block(const float2 *buf, const float2 *__restrict__ tw,
+                                               int tid, Consume consume) {
+  constexpr int NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT;
+  constexpr int PS = FftPad<N>::PS;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = tid + q * NT;
+    if ((TOT % NT) == 0 || idx < TOT) {
+      int f, j;
+      fj_of<F, NB, JF>(idx, f, j);
+      float2 v[R];
+      fft_gather<N, R, NS, S, PS>(buf, tw, f, j, v);
+      dft<R>(v);
+      consume(f, (j / NS) * NS * R + (j % NS), NS, v);
+    }
+  }
+}
+
+// As fft_inverse, with the last pass handing whole butterflies to consume().
+template <int N, int F, int NT, int S, bool JF, class Load, class Consume>
+__device__ __forceinline__ void fft_inverse_blocks(float2 *buf, const float2 *__restrict__ tw,
+                                                   int tid, Load load, Consume consume) {
+  using Sh = FftShape<N>;
+  fft_first<N, F, NT, S, JF>(buf, tid, load);
+  if constexpr (Sh::R2 == 1) {
+    fft_last_block<N, Sh::R1, Sh::R0, F, NT, S, JF>(buf, tw, tid, consume);
   } else {
-    stockham_pass<N, 16, 1, F, NT, STRIDE, PS>(buf, tw, tid);
-    stockham_pass<N, 16, 16, F, NT, STRIDE, PS>(buf, tw, tid);
-    stockham_pass<N, 8, 256, F, NT, STRIDE, PS>(buf, tw, tid);
+    fft_mid<N, Sh::R1, Sh::R0, F, NT, S, JF>(buf, tw, tid);
+    fft_last_block<N, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF>(buf, tw, tid, consume);
+  }
+}
+
+// Inverse (exp(+i)) unnormalised FFT of F sequences of length N: inputs from
+// load(f, i), outputs to store(f, k, value), LDS buf of F * S elements
+// (S >= FftPad<N>::PADDED) for the exchanges between passes.
+template <int N, int F, int NT, int S, bool JF, class Load, class Store>
+__device__ __forceinline__ void fft_inverse(float2 *buf, const float2 *__restrict__ tw, int tid,
+                                            Load load, Store store) {
+  using Sh = FftShape<N>;
+  fft_first<N, F, NT, S, JF>(buf, tid, load);
+  if constexpr (Sh::R2 == 1) {
+    fft_last<N, Sh::R1, Sh::R0, F, NT, S, JF>(buf, tw, tid, store);
+  } else {
+    fft_mid<N, Sh::R1, Sh::R0, F, NT, S, JF>(buf, tw, tid);
+    fft_last<N, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF>(buf, tw, tid, store);
   }
 }
 
@@ -195,44 +322,16 @@ __device__ __forceinline__ float2 zval(float2 a, float2 am, float2 b, float2 bm,
 
 // Launch shapes of the two imaging passes for image side N.
 template <int N>
-struct RowCfg {
+struct RowCfg {  // dense rows: F grid rows per workgroup
   static constexpr int NT = 512;
-  static constexpr int F = (8192 / N) < 64 ? (8192 / N) : 64;  // rows per workgroup
-  static constexpr int STRIDE = FftShape<N>::PADDED;
+  static constexpr int F = (8192 / N) < 64 ? (8192 / N) : 64;
+  static constexpr int STRIDE = FftPad<N>::PADDED;
 };
 template <int N>
-struct ColCfg {
-  static constexpr int NT = 1024;
-  static constexpr int COLS = (16384 / N) < N ? (16384 / N) : N;  // columns per workgroup
-  static constexpr int STRIDE = FftShape<N>::PADDED + 1;          // odd: spreads the transpose
+struct ColCfg {  // columns: COLS columns per workgroup (~68 KB LDS: two workgroups per CU)
+  static constexpr int COLS = N >= 2048 ? 4 : (N >= 1024 ? 8 : (N >= 512 ? 16 : 32 < N ? 32 : N));
+  static constexpr int NT = COLS * N / FftShape<N>::R0 < 256 ? 256 : COLS * N / FftShape<N>::R0;
+  static constexpr int STRIDE = FftPad<N>::PADDED + 1;  // odd: neighbouring columns on other banks
 };
-
-// Column tile of the row-transformed data: buf[x][pidx(v)] = M[slot(v)][x0 + x]
-// (zero for rows without samples), COLS columns.  The trip count is a
-// compile-time constant so every thread issues all of its loads before it
-// stores any of them.
-template <int N>
-__device__ __forceinline__ void load_col_tile(const float2 *__restrict__ Mp,
-                                              const int32_t *__restrict__ row_slot, float2 *buf,
-                                              int tid) {
-  constexpr int COLS = ColCfg<N>::COLS, NT = ColCfg<N>::NT, S = ColCfg<N>::STRIDE;
-  constexpr int PS = FftShape<N>::PS;
-  constexpr int Q = (N * COLS + NT - 1) / NT;
-  float2 v[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = tid + q * NT;
-    v[q] = make_float2(0.f, 0.f);
-    if ((N * COLS) % NT == 0 || e < N * COLS) {
-      const int slot = row_slot[e / COLS];
-      if (slot >= 0) v[q] = Mp[(size_t)slot * N + e % COLS];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = tid + q * NT;
-    if ((N * COLS) % NT == 0 || e < N * COLS) buf[(e % COLS) * S + pidx<PS>(e / COLS)] = v[q];
-  }
-}
 
 }  // namespace rf

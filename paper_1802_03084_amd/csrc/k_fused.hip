@@ -34,7 +34,11 @@ using namespace rf;
 
 constexpr int kMaxW = 8;               // widths handled by one pass over the segment
 constexpr float kMedOverRms = 0.6745f; // median |x| / rms of a zero-mean Gaussian
-constexpr float kBracket = 0.01f;      // half-width of the median bracket (relative)
+// half-width of the median bracket (relative): the bracket holds about 0.86%
+// of the pixels per percent of half-width; larger images have a tighter
+// median/rms ratio and get a narrower bracket so the kept values fit in LDS
+template <int N>
+constexpr float bracket_of() { return N >= 2048 ? 0.004f : 0.01f; }
 constexpr int kDrsThreads = 256;
 constexpr int kSelThreads = 256;
 constexpr size_t kAlign = 256;
@@ -50,9 +54,9 @@ struct WidthSet {
 struct ColPart {   // per (image, column workgroup)
   float maxv;
   int32_t maxi;
-  uint32_t cnt_lo;
-  uint32_t n;      // values inside the bracket (may exceed the region size)
-  float lo, hi;    // the bracket [lo, hi) (identical in every workgroup of a pair)
+  uint32_t cnt_lo;  // pixels with |value| below the bracket
+  uint32_t n;       // pixels inside the bracket (values kept: min(n, region capacity))
+  float lo, hi;     // the bracket [lo, hi) (identical in every workgroup of a pair)
 };
 
 __device__ __forceinline__ bool better(float v, int i, float bv, int bi) {
@@ -104,34 +108,48 @@ __global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis
     a1[j] = a0[j];
     cnt[j] = 0;
   }
-  for (int t = t0; t < t1; ++t) {
-    const int src = t + d;
-    float2 v0 = make_float2(0.f, 0.f), v1 = v0;
-    if (src < nint) load_pols(vis, (size_t)src * nbc + bc, P, v0, v1);
+  constexpr int U = 8;  // integrations loaded ahead: U loads in flight per thread
+  for (int tb = t0; tb < t1; tb += U) {
+    float2 w0[U], w1[U];
 #pragma unroll
-    for (int j = 0; j < kMaxW; ++j) {
-      if (j < ws.nw) {
-        a0[j].x += v0.x;
-        a0[j].y += v0.y;
-        if (P == 2) {
-          a1[j].x += v1.x;
-          a1[j].y += v1.y;
-        }
-        if (++cnt[j] == ws.w[j]) {
-          const int k = (t + 1) / ws.w[j] - 1;
-          const float fw = (float)ws.w[j];
-          float2 vi;
+    for (int u = 0; u < U; ++u) {  // branch-free: clamp the address, zero the value
+      const int src = tb + u + d;
+      float2 a, b = make_float2(0.f, 0.f);
+      load_pols(vis, (size_t)min(src, nint - 1) * nbc + bc, P, a, b);
+      const bool ok = src < nint;
+      w0[u] = ok ? a : make_float2(0.f, 0.f);
+      w1[u] = ok ? b : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = tb + u;
+      if (t >= t1) break;
+      const float2 v0 = w0[u], v1 = w1[u];
+#pragma unroll
+      for (int j = 0; j < kMaxW; ++j) {
+        if (j < ws.nw) {
+          a0[j].x += v0.x;
+          a0[j].y += v0.y;
           if (P == 2) {
-            const float r0x = a0[j].x / fw, r0y = a0[j].y / fw;
-            const float r1x = a1[j].x / fw, r1y = a1[j].y / fw;
-            vi = make_float2((r0x + r1x) * 0.5f, (r0y + r1y) * 0.5f);
-          } else {
-            vi = make_float2(a0[j].x / fw, a0[j].y / fw);
+            a1[j].x += v1.x;
+            a1[j].y += v1.y;
           }
-          ws.out[j][(size_t)k * nbc + bc] = vi;
-          a0[j] = make_float2(0.f, 0.f);
-          a1[j] = a0[j];
-          cnt[j] = 0;
+          if (++cnt[j] == ws.w[j]) {
+            const int k = (t + 1) / ws.w[j] - 1;
+            const float fw = (float)ws.w[j];
+            float2 vi;
+            if (P == 2) {
+              const float r0x = a0[j].x / fw, r0y = a0[j].y / fw;
+              const float r1x = a1[j].x / fw, r1y = a1[j].y / fw;
+              vi = make_float2((r0x + r1x) * 0.5f, (r0y + r1y) * 0.5f);
+            } else {
+              vi = make_float2(a0[j].x / fw, a0[j].y / fw);
+            }
+            ws.out[j][(size_t)k * nbc + bc] = vi;
+            a0[j] = make_float2(0.f, 0.f);
+            a1[j] = a0[j];
+            cnt[j] = 0;
+          }
         }
       }
     }
@@ -141,37 +159,87 @@ __global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis
 // ------------------------------------------------------------------ rows
 // Gridding as a gather: CV[i][c] = sum of the Stokes I samples of uv cell c
 // for image i of a batch, in the plan's contributor order (the same sums as
-// rf_grid).  All blocks of one image run on one XCD (blocks are dealt to the
-// eight XCDs round robin), so the image's samples stay in that XCD's L2 while
-// its cells gather them.
+// rf_grid).  A workgroup takes a block of whole cells (at most 1024
+// contributors) for a group of kCellImgs images: it stages the block's
+// samples in LDS with all loads in flight, then one thread per cell sums them
+// in contributor order.  All blocks of one image group run on one XCD (blocks
+// are dealt to the eight XCDs round robin), so the group's samples stay in
+// that XCD's L2.
 constexpr int kCellThreads = 256;
+constexpr int kCellImgs = 4;       // images per workgroup: contributor indices loaded once
+constexpr int kCellBlock = 1024;   // contributors staged per workgroup
 
 __global__ __launch_bounds__(kCellThreads) void k_cellsum(
-    const float2 *__restrict__ vi, int nbc, int k0, int nimg, int n_cells, int bpi,
-    const int32_t *__restrict__ coff, const int32_t *__restrict__ contrib,
-    float2 *__restrict__ cv) {
+    const float2 *__restrict__ vi, int nbc, int k0, int nimg, int n_cells, int n_cblk,
+    const int32_t *__restrict__ cblk, const int32_t *__restrict__ coff,
+    const int32_t *__restrict__ contrib, float2 *__restrict__ cv) {
+  __shared__ float2 val[kCellBlock * kCellImgs];
   const int b = blockIdx.x, xcd = b & 7, local = b >> 3;
-  const int il = (local / bpi) * 8 + xcd;  // image within the batch
-  const int c = (local % bpi) * kCellThreads + threadIdx.x;
-  if (il >= nimg || c >= n_cells) return;
-  const float2 *v = vi + (size_t)(k0 + il) * nbc;
-  float2 acc = make_float2(0.f, 0.f);
-  const int e = coff[c + 1];
-  for (int q = coff[c]; q < e; q += 4) {  // four independent loads in flight
-    int b[4];
-    float2 x[4];
+  const int g = (local / n_cblk) * 8 + xcd;  // group of kCellImgs images within the batch
+  const int blk = local % n_cblk;
+  const int i0 = g * kCellImgs;
+  if (i0 >= nimg) return;
+  const int tid = threadIdx.x;
+  const float2 *v = vi + (size_t)(k0 + i0) * nbc;
+  const int c0 = cblk[blk], c1 = cblk[blk + 1];
+  const int q0 = coff[c0], q1 = coff[c1], nq = q1 - q0;
+  if (nq <= kCellBlock) {
+    // stage the block's samples: every index load, then every value load, in flight together
+    constexpr int T = kCellBlock / kCellThreads;
+    int bq[T];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) b[i] = q + i < e ? contrib[q + i] : -1;
+    for (int t = 0; t < T; ++t) bq[t] = contrib[min(q0 + tid + t * kCellThreads, q1 - 1)];
+    float2 x[T][kCellImgs];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) x[i] = b[i] >= 0 ? v[b[i]] : make_float2(0.f, 0.f);
+    for (int t = 0; t < T; ++t)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (b[i] >= 0) {
-        acc.x += x[i].x;
-        acc.y += x[i].y;
+      for (int m = 0; m < kCellImgs; ++m)
+        x[t][m] = v[(size_t)min(m, nimg - 1 - i0) * nbc + bq[t]];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int q = tid + t * kCellThreads;
+      if (q < nq)
+#pragma unroll
+        for (int m = 0; m < kCellImgs; ++m) val[q * kCellImgs + m] = x[t][m];
+    }
+    __syncthreads();
+    for (int c = c0 + tid; c < c1; c += kCellThreads) {
+      float2 acc[kCellImgs];
+#pragma unroll
+      for (int m = 0; m < kCellImgs; ++m) acc[m] = make_float2(0.f, 0.f);
+      const int e = coff[c + 1] - q0;
+      for (int q = coff[c] - q0; q < e; ++q)
+#pragma unroll
+        for (int m = 0; m < kCellImgs; ++m) {
+          const float2 y = val[q * kCellImgs + m];
+          acc[m].x += y.x;
+          acc[m].y += y.y;
+        }
+#pragma unroll
+      for (int m = 0; m < kCellImgs; ++m)
+        if (i0 + m < nimg) cv[(size_t)(i0 + m) * n_cells + c] = acc[m];
+    }
+  } else {
+    // a cell with more contributors than a block: direct gather, same order
+    for (int c = c0 + tid; c < c1; c += kCellThreads) {
+      float2 acc[kCellImgs];
+#pragma unroll
+      for (int m = 0; m < kCellImgs; ++m) acc[m] = make_float2(0.f, 0.f);
+      const int e = coff[c + 1];
+      for (int q = coff[c]; q < e; ++q) {
+        const int bcq = contrib[q];
+#pragma unroll
+        for (int m = 0; m < kCellImgs; ++m) {
+          const float2 y = v[(size_t)min(m, nimg - 1 - i0) * nbc + bcq];
+          acc[m].x += y.x;
+          acc[m].y += y.y;
+        }
       }
+#pragma unroll
+      for (int m = 0; m < kCellImgs; ++m)
+        if (i0 + m < nimg) cv[(size_t)(i0 + m) * n_cells + c] = acc[m];
+    }
   }
-  cv[(size_t)il * n_cells + c] = acc;
 }
 
 // Row pass.  A workgroup takes one row pair {v, -v} for a block of PBW image
@@ -182,10 +250,10 @@ __global__ __launch_bounds__(kCellThreads) void k_cellsum(
 // pass.
 template <int N>
 struct RowPairCfg {
-  static constexpr int NT = 512;
-  static constexpr int PBW = N >= 2048 ? 4 : 8;  // image pairs per workgroup
+  static constexpr int PBW = N >= 2048 ? 2 : 4;  // image pairs per workgroup (~68 KB LDS)
   static constexpr int F = 2 * PBW;              // transforms per workgroup
-  static constexpr int STRIDE = FftShape<N>::PADDED;
+  static constexpr int NT = F * N / FftShape<N>::R0 < 256 ? 256 : F * N / FftShape<N>::R0;
+  static constexpr int STRIDE = FftPad<N>::PADDED;
 };
 
 template <int N>
@@ -194,12 +262,11 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
     const int32_t *__restrict__ rp_row, const int32_t *__restrict__ rp_sa,
     const int32_t *__restrict__ rp_sb, int n_rp, int n_rows, const int32_t *__restrict__ zs_off,
     const int32_t *__restrict__ zs_u, const int32_t *__restrict__ zs_ck,
-    const int32_t *__restrict__ zs_cmk, const float2 *__restrict__ tw_g, float2 *__restrict__ M,
+    const int32_t *__restrict__ zs_cmk, const float2 *__restrict__ tw, float2 *__restrict__ M,
     float *__restrict__ epart) {
   constexpr int PBW = RowPairCfg<N>::PBW, F = RowPairCfg<N>::F, NT = RowPairCfg<N>::NT;
-  constexpr int S = RowPairCfg<N>::STRIDE, PS = FftShape<N>::PS;
+  constexpr int S = RowPairCfg<N>::STRIDE, PS = FftPad<N>::PS;
   __shared__ float2 buf[F * S];
-  __shared__ float2 tw[N];
   __shared__ float s_e[2 * PBW];
   const int rp = blockIdx.x % n_rp;
   const int pb0 = (blockIdx.x / n_rp) * PBW;  // first pair of this block, batch-local
@@ -207,7 +274,6 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
   const int r = rp_row[rp];
   const int rm = (N - r) & (N - 1);
   const bool two = rm != r;
-  for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
   for (int i = tid; i < F * S; i += NT) buf[i] = make_float2(0.f, 0.f);
   if (tid < 2 * PBW) s_e[tid] = 0.f;
   __syncthreads();
@@ -223,11 +289,13 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
     const int u = zs_u[z], ck = zs_ck[z], cmk = zs_cmk[z];
     const float2 zero = make_float2(0.f, 0.f);
     const float2 *ca = cv + (size_t)ib * n_cells;
-    const float2 *cb = ca + n_cells;
-    const float2 ga = ck >= 0 ? ca[ck] : zero;
-    const float2 gam = cmk >= 0 ? ca[cmk] : zero;
-    const float2 gb = (hasb && ck >= 0) ? cb[ck] : zero;
-    const float2 gbm = (hasb && cmk >= 0) ? cb[cmk] : zero;
+    const float2 *cb = hasb ? ca + n_cells : ca;
+    const float2 xa = ca[max(ck, 0)], xam = ca[max(cmk, 0)];  // branch-free loads
+    const float2 xb = cb[max(ck, 0)], xbm = cb[max(cmk, 0)];
+    const float2 ga = ck >= 0 ? xa : zero;
+    const float2 gam = cmk >= 0 ? xam : zero;
+    const float2 gb = (hasb && ck >= 0) ? xb : zero;
+    const float2 gbm = (hasb && cmk >= 0) ? xbm : zero;
     const float sg = ((r + u) & 1) ? -0.5f : 0.5f;
     buf[pp * S + pidx<PS>(u)] = zval(ga, gam, gb, gbm, sg);
     if (two) buf[(PBW + pp) * S + pidx<PS>((N - u) & (N - 1))] = zval(gam, ga, gbm, gb, sg);
@@ -239,33 +307,29 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
   __syncthreads();
   if (tid < 2 * PBW && pb0 + tid / 2 < pbn)
     epart[((size_t)(pb0 + tid / 2) * n_rp + rp) * 2 + (tid & 1)] = s_e[tid];
-  fft_inverse<N, F, NT, S>(buf, tw, tid);
   const int sa = rp_sa[rp], sb = rp_sb[rp];
-  for (int e = tid; e < F * N; e += NT) {
-    const int f = e / N, x = e % N;
-    const int side = f / PBW, pp = f % PBW;
-    const int pl = pb0 + pp;
-    if (pl >= pbn || (side == 1 && !two)) continue;
-    const int slot = side ? sb : sa;
-    M[((size_t)pl * n_rows + slot) * N + x] = buf[f * S + pidx<PS>(x)];
-  }
+  fft_inverse<N, F, NT, S, true>(
+      buf, tw, tid, [&](int f, int i) { return buf[f * S + pidx<PS>(i)]; },
+      [&](int f, int x, float2 v) {
+        const int side = f / PBW, pp = f % PBW;
+        const int pl = pb0 + pp;
+        if (pl < pbn && (side == 0 || two))
+          M[((size_t)pl * n_rows + (side ? sb : sa)) * N + x] = v;
+      });
 }
 
 // ------------------------------------------------------------------ columns
 template <int N>
 __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
-    const float2 *__restrict__ M, int n_rows, const int32_t *__restrict__ row_slot, int nimg_w,
-    int p0, int pbn, float inv_w, const float2 *__restrict__ tw_g,
-    const float *__restrict__ epart, int n_rp, ColPart *__restrict__ part,
-    float *__restrict__ list, int reg) {
+    const float2 *__restrict__ M, int n_rows, int vmax, int nimg_w,
+    int p0, int pbn, float inv_w, const float2 *__restrict__ tw, const float *__restrict__ epart,
+    int n_rp, ColPart *__restrict__ part, float *__restrict__ list, int capb) {
   constexpr int COLS = ColCfg<N>::COLS, NT = ColCfg<N>::NT, S = ColCfg<N>::STRIDE;
-  constexpr int PS = FftShape<N>::PS;
   constexpr int CB = N / COLS;
   constexpr int NW = NT / 64;
   __shared__ float2 buf[COLS * S];
-  __shared__ float2 tw[N];
   __shared__ float s_br[4];
-  __shared__ uint32_t s_n[2];
+  __shared__ uint32_t s_cnt[2];
   __shared__ float w_v[2][NW];
   __shared__ int32_t w_i[2][NW];
   __shared__ uint32_t w_c[2][NW];
@@ -274,7 +338,6 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
   if (pl >= pbn) return;
   const int tid = threadIdx.x;
   const int x0 = cb * COLS;
-  for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
   if (tid < 64) {
     float ea = 0.f, eb = 0.f;
     for (int r = tid; r < n_rp; r += 64) {
@@ -288,52 +351,84 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
     }
     if (tid < 2) {
       const float m = kMedOverRms * (sqrtf(tid == 0 ? ea : eb) * inv_w);
-      s_br[2 * tid + 0] = m * (1.0f - kBracket);
-      s_br[2 * tid + 1] = m * (1.0f + kBracket);
-      s_n[tid] = 0;
+      s_br[2 * tid + 0] = m * (1.0f - bracket_of<N>());
+      s_br[2 * tid + 1] = m * (1.0f + bracket_of<N>());
+      s_cnt[tid] = 0;
     }
   }
-  load_col_tile<N>(M + (size_t)pl * n_rows * N + x0, row_slot, buf, tid);
   __syncthreads();
-  fft_inverse<N, COLS, NT, S>(buf, tw, tid);
   const bool hasb = 2 * (p0 + pl) + 1 < nimg_w;
   const float lo_a = s_br[0], hi_a = s_br[1], lo_b = s_br[2], hi_b = s_br[3];
-  float *la = list + ((size_t)(2 * pl) * CB + cb) * reg;
-  float *lb = list + ((size_t)(2 * pl + 1) * CB + cb) * reg;
+  // this workgroup's list regions (capb values each) for the two images
+  float *la = list + ((size_t)(2 * pl) * CB + cb) * capb;
+  float *lb = list + ((size_t)(2 * pl + 1) * CB + cb) * capb;
   float bva = -__builtin_inff(), bvb = -__builtin_inff();
   int bia = 0x7fffffff, bib = 0x7fffffff;
   uint32_t ca = 0, cbn = 0;
-  for (int e = tid; e < N * COLS; e += NT) {
-    const int y = e / COLS, x = e % COLS;
-    const float2 v = buf[x * S + pidx<PS>(y)];
-    const int idx = y * N + x0 + x;
-    const float pa = v.x * inv_w;
-    if (better(pa, idx, bva, bia)) {
-      bva = pa;
-      bia = idx;
-    }
-    const float aa = fabsf(pa);
-    if (aa < lo_a) {
-      ++ca;
-    } else if (aa < hi_a) {
-      const uint32_t pos = atomicAdd(&s_n[0], 1u);
-      if (pos < (uint32_t)reg) la[pos] = aa;
-    }
-    if (hasb) {
-      const float pb = v.y * inv_w;
-      if (better(pb, idx, bvb, bib)) {
-        bvb = pb;
-        bib = idx;
-      }
-      const float ab = fabsf(pb);
-      if (ab < lo_b) {
-        ++cbn;
-      } else if (ab < hi_b) {
-        const uint32_t pos = atomicAdd(&s_n[1], 1u);
-        if (pos < (uint32_t)reg) lb[pos] = ab;
-      }
-    }
-  }
+  const float2 *Mp = M + (size_t)pl * n_rows * N + x0;
+  const int lane = tid & 63;
+  fft_inverse_blocks<N, COLS, NT, S, false>(
+      buf, tw, tid,
+      [&](int f, int i) {  // branch-free: every load is issued before any is used
+        const int slot = band_slot(i, N, vmax);
+        const float2 m = Mp[(size_t)max(slot, 0) * N + f];
+        return slot >= 0 ? m : make_float2(0.f, 0.f);
+      },
+      [&](int f, int k0, int ks, auto &v) {
+        constexpr int R = sizeof(v) / sizeof(v[0]);
+        uint32_t ma = 0, mb = 0;  // bracket membership, one bit per output
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int idx = (k0 + r * ks) * N + x0 + f;
+          const float pa = v[r].x * inv_w;
+          if (pa > bva || (pa == bva && idx < bia)) {
+            bva = pa;
+            bia = idx;
+          }
+          const float aa = fabsf(pa);
+          ca += aa < lo_a;
+          ma |= (aa >= lo_a && aa < hi_a) ? (1u << r) : 0u;
+          if (hasb) {
+            const float pb = v[r].y * inv_w;
+            if (pb > bvb || (pb == bvb && idx < bib)) {
+              bvb = pb;
+              bib = idx;
+            }
+            const float ab = fabsf(pb);
+            cbn += ab < lo_b;
+            mb |= (ab >= lo_b && ab < hi_b) ? (1u << r) : 0u;
+          }
+        }
+        // reserve list space once per wave, then write this thread's values
+        const uint32_t na = __popc(ma), nb = __popc(mb);
+        uint32_t pa_ = na, pb_ = nb;  // inclusive prefix sums over the wave
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t ya = __shfl_up(pa_, o, 64), yb = __shfl_up(pb_, o, 64);
+          if (lane >= o) {
+            pa_ += ya;
+            pb_ += yb;
+          }
+        }
+        uint32_t basea = 0, baseb = 0;
+        if (lane == 63) {  // one reservation per wave and image, in LDS
+          basea = pa_ ? atomicAdd(&s_cnt[0], pa_) : 0u;
+          baseb = pb_ ? atomicAdd(&s_cnt[1], pb_) : 0u;
+        }
+        basea = __shfl(basea, 63, 64) + pa_ - na;
+        baseb = __shfl(baseb, 63, 64) + pb_ - nb;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (ma & (1u << r)) {
+            if (basea < (uint32_t)capb) la[basea] = fabsf(v[r].x * inv_w);
+            ++basea;
+          }
+          if (mb & (1u << r)) {
+            if (baseb < (uint32_t)capb) lb[baseb] = fabsf(v[r].y * inv_w);
+            ++baseb;
+          }
+        }
+      });
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const float ova = __shfl_xor(bva, o, 64);
@@ -376,7 +471,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
     cp.maxv = v;
     cp.maxi = i;
     cp.cnt_lo = c;
-    cp.n = s_n[tid];
+    cp.n = s_cnt[tid];
     cp.lo = s_br[2 * tid + 0];
     cp.hi = s_br[2 * tid + 1];
     part[(size_t)(2 * pl + tid) * CB + cb] = cp;
@@ -427,23 +522,34 @@ __device__ __forceinline__ void sel_bin(const uint32_t *hist, uint32_t rank, uin
   __syncthreads();
 }
 
+constexpr int kMaxCB = 512;       // column workgroups per image, at most
+constexpr int kLdsVals = 20480;   // bracket values staged in LDS (80 KB)
+constexpr int kLoadGroup = 8;     // list regions a wave loads at once
+
+// Per image: combines the column workgroups' records (peak, count below the
+// bracket, bracket counts), stages every kept bracket value in LDS, and finds
+// the median |value| among them.  Images whose median is not inside the
+// bracket, or whose bracket values did not all fit, go to the exact fallback.
 __global__ __launch_bounds__(kSelThreads) void k_select(
-    const ColPart *__restrict__ part, const float *__restrict__ list, int cbn, int reg,
-    int nimg_w, int p0, int pbn, int npix, int dm_idx, int width_idx, int width,
-    int64_t stat_base, rf_image_stats *__restrict__ stats, rf_candidate *__restrict__ cand,
-    int cap, int32_t *__restrict__ ncand, int32_t *__restrict__ fb_count,
-    int32_t *__restrict__ fb_list, float thr, int t_begin, int t_end) {
+    const ColPart *__restrict__ part, const float *__restrict__ list, int cbn, int capb,
+    int nimg_w, int p0, int pbn, int npix, int dm_idx,
+    int width_idx, int width, int64_t stat_base, rf_image_stats *__restrict__ stats,
+    rf_candidate *__restrict__ cand, int ncap, int32_t *__restrict__ ncand,
+    int32_t *__restrict__ fb_count, int32_t *__restrict__ fb_list, float thr, int t_begin,
+    int t_end) {
   __shared__ uint32_t hist[kBins];
-  __shared__ uint32_t cnt[256];
   __shared__ uint32_t wsum[kSelThreads / 64];
   __shared__ uint32_t sel[2];
   __shared__ float w_v[kSelThreads / 64];
   __shared__ int32_t w_i[kSelThreads / 64];
-  __shared__ uint32_t w_lo[kSelThreads / 64], w_n[kSelThreads / 64], w_o[kSelThreads / 64];
+  __shared__ uint32_t w_lo[kSelThreads / 64];
+  __shared__ uint32_t w_n[kSelThreads / 64];
+  __shared__ uint32_t w_of[kSelThreads / 64];
   __shared__ float s_v;
   __shared__ int32_t s_i;
-  __shared__ uint32_t s_lo, s_n;
-  __shared__ int s_ovf;
+  __shared__ uint32_t s_lo, s_n, s_of;
+  __shared__ uint32_t r_cnt[kMaxCB], r_off[kMaxCB];
+  __shared__ float vals[kLdsVals];
   __shared__ float binv[kBinCap];
   __shared__ uint32_t s_nc;
   __shared__ float s_med;
@@ -451,23 +557,33 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
   const int pl = il >> 1;
   const int k = 2 * (p0 + pl) + (il & 1);
   if (pl >= pbn || k >= nimg_w) return;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const ColPart *pp = part + (size_t)il * cbn;
-  {  // combine the column workgroups' records (cbn <= 256 = kSelThreads)
+  {  // combine the column workgroups' records; region r holds r_cnt[r] values
+     // placed at r_off[r] in LDS (kMaxCB / kSelThreads consecutive regions per thread)
+    constexpr int RPT = kMaxCB / kSelThreads;
     float v = -__builtin_inff();
     int32_t i = 0x7fffffff;
-    uint32_t lo = 0, n = 0, ovf = 0;
-    if (tid < cbn) {
-      const ColPart c = pp[tid];
-      v = c.maxv;
-      i = c.maxi;
-      lo = c.cnt_lo;
-      n = min(c.n, (uint32_t)reg);
-      ovf = c.n > (uint32_t)reg;
-      cnt[tid] = n;
-    }
+    uint32_t lo = 0, nn = 0, of = 0, cnt[RPT];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int q = 0; q < RPT; ++q) {
+      const int r = RPT * tid + q;
+      cnt[q] = 0;
+      if (r < cbn) {
+        const ColPart c = pp[r];
+        if (better(c.maxv, c.maxi, v, i)) {
+          v = c.maxv;
+          i = c.maxi;
+        }
+        lo += c.cnt_lo;
+        cnt[q] = c.n;
+        nn += c.n;
+        of |= c.n > (uint32_t)capb;
+      }
+    }
+    uint32_t inc = nn;  // inclusive scan of the bracket counts over the block
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
       const float ov = __shfl_xor(v, o, 64);
       const int32_t oi = __shfl_xor(i, o, 64);
       if (better(ov, oi, v, i)) {
@@ -475,18 +591,33 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
         i = oi;
       }
       lo += __shfl_xor(lo, o, 64);
-      n += __shfl_xor(n, o, 64);
-      ovf |= __shfl_xor(ovf, o, 64);
+      of |= __shfl_xor(of, o, 64);
+      const uint32_t y = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += y;
     }
-    const int wid = tid >> 6;
-    if ((tid & 63) == 0) {
+    if (lane == 63) w_n[wid] = inc;
+    if (lane == 0) {
       w_v[wid] = v;
       w_i[wid] = i;
       w_lo[wid] = lo;
-      w_n[wid] = n;
-      w_o[wid] = ovf;
+      w_of[wid] = of;
     }
     __syncthreads();
+    uint32_t add = 0, tot = 0;
+    for (int w = 0; w < kSelThreads / 64; ++w) {
+      add += w < wid ? w_n[w] : 0u;
+      tot += w_n[w];
+    }
+    uint32_t at = add + inc - nn;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = RPT * tid + q;
+      if (r < cbn) {
+        r_cnt[r] = cnt[q];
+        r_off[r] = at;
+        at += cnt[q];
+      }
+    }
     if (tid == 0) {
       for (int w = 1; w < kSelThreads / 64; ++w) {
         if (better(w_v[w], w_i[w], v, i)) {
@@ -494,26 +625,51 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
           i = w_i[w];
         }
         lo += w_lo[w];
-        n += w_n[w];
-        ovf |= w_o[w];
+        of |= w_of[w];
       }
       s_v = v;
       s_i = i;
       s_lo = lo;
-      s_n = n;
-      s_ovf = (int)ovf;
+      s_n = tot;
+      s_of = of;
     }
   }
   __syncthreads();
   const float peak = s_v;
   const int32_t pidx_ = s_i;
   const uint32_t rank = (uint32_t)(((size_t)npix * npix - 1) / 2);
+  const uint32_t n = s_n;
+  const bool ovf = s_of != 0 || n > (uint32_t)kLdsVals;
   float med;
-  if (peak == 0.f && s_lo == 0 && s_n == 0) {
+  if (peak == 0.f && s_lo == 0 && n == 0) {
     med = 0.f;  // identically zero image (every pixel equals the zero peak)
-  } else if (!s_ovf && s_lo <= rank && rank < s_lo + s_n) {
+  } else if (!ovf && s_lo <= rank && rank < s_lo + n) {
     uint32_t r = rank - s_lo;
-    const float *lp = list + (size_t)il * cbn * reg;
+    // stage the regions in LDS: a wave takes kLoadGroup regions at a time with
+    // their first 128 values' loads all in flight (regions hold ~70 values)
+    const float *lr = list + (size_t)il * cbn * capb;
+    constexpr int NWV = kSelThreads / 64;
+    for (int g0 = wid; g0 < cbn; g0 += NWV * kLoadGroup) {
+      float x0[kLoadGroup], x1[kLoadGroup];
+#pragma unroll
+      for (int u = 0; u < kLoadGroup; ++u) {
+        const int rg = min(g0 + u * NWV, cbn - 1);
+        const float *rp = lr + (size_t)rg * capb;
+        x0[u] = rp[lane];
+        x1[u] = rp[lane + 64];
+      }
+#pragma unroll
+      for (int u = 0; u < kLoadGroup; ++u) {
+        const int rg = g0 + u * NWV;
+        if (rg < cbn) {
+          const uint32_t c = r_cnt[rg], o = r_off[rg];
+          if ((uint32_t)lane < c) vals[o + lane] = x0[u];
+          if ((uint32_t)lane + 64 < c) vals[o + lane + 64] = x1[u];
+          for (uint32_t e = lane + 128; e < c; e += 64) vals[o + e] = lr[(size_t)rg * capb + e];
+        }
+      }
+    }
+    const float *lp = vals;
     // pass 1: 2048 equal-width bins over the bracket [lo, hi); the bin index
     // is a monotone function of the value, so the bin holding rank r holds
     // the wanted order statistic
@@ -521,28 +677,20 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
     const float scale = (float)kBins / (hi - lo);
     for (int i = tid; i < kBins; i += kSelThreads) hist[i] = 0;
     if (tid == 0) s_nc = 0;
-    __syncthreads();
-    for (int g = 0; g < cbn; ++g) {
-      const uint32_t ng = cnt[g];
-      for (uint32_t e = tid; e < ng; e += kSelThreads) {
-        const float v = lp[(size_t)g * reg + e];
-        atomicAdd(&hist[min(kBins - 1, (int)((v - lo) * scale))], 1u);
-      }
-    }
+    __syncthreads();  // also: every staged value is in LDS
+    for (uint32_t e = tid; e < n; e += kSelThreads)
+      atomicAdd(&hist[min(kBins - 1, (int)((lp[e] - lo) * scale))], 1u);
     __syncthreads();
     sel_bin(hist, r, wsum, sel);
     const int b1 = (int)sel[0];
     const uint32_t r1 = sel[1];
     __syncthreads();
     // pass 2: gather that bin's values and rank them directly
-    for (int g = 0; g < cbn; ++g) {
-      const uint32_t ng = cnt[g];
-      for (uint32_t e = tid; e < ng; e += kSelThreads) {
-        const float v = lp[(size_t)g * reg + e];
-        if (min(kBins - 1, (int)((v - lo) * scale)) == b1) {
-          const uint32_t at = atomicAdd(&s_nc, 1u);
-          if (at < kBinCap) binv[at] = v;
-        }
+    for (uint32_t e = tid; e < n; e += kSelThreads) {
+      const float v = lp[e];
+      if (min(kBins - 1, (int)((v - lo) * scale)) == b1) {
+        const uint32_t at = atomicAdd(&s_nc, 1u);
+        if (at < kBinCap) binv[at] = v;
       }
     }
     __syncthreads();
@@ -566,17 +714,14 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
       for (int pass = 0; pass < 3; ++pass) {
         for (int i = tid; i < kBins; i += kSelThreads) hist[i] = 0;
         __syncthreads();
-        for (int g = 0; g < cbn; ++g) {
-          const uint32_t ng = cnt[g];
-          for (uint32_t e = tid; e < ng; e += kSelThreads) {
-            const uint32_t key = __float_as_uint(lp[(size_t)g * reg + e]);
-            if (pass == 0) {
-              atomicAdd(&hist[key >> 20], 1u);
-            } else if (pass == 1) {
-              if ((key >> 20) == prefix) atomicAdd(&hist[(key >> 9) & 2047u], 1u);
-            } else {
-              if ((key >> 9) == prefix) atomicAdd(&hist[key & 511u], 1u);
-            }
+        for (uint32_t e = tid; e < n; e += kSelThreads) {
+          const uint32_t key = __float_as_uint(lp[e]);
+          if (pass == 0) {
+            atomicAdd(&hist[key >> 20], 1u);
+          } else if (pass == 1) {
+            if ((key >> 20) == prefix) atomicAdd(&hist[(key >> 9) & 2047u], 1u);
+          } else {
+            if ((key >> 9) == prefix) atomicAdd(&hist[key & 511u], 1u);
           }
         }
         __syncthreads();
@@ -611,7 +756,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
     const int t_int = k * width;
     if (snr > thr && t_int >= t_begin && t_int < t_end) {
       const int slot = atomicAdd(ncand, 1);
-      if (slot < cap) {
+      if (slot < ncap) {
         rf_candidate c;
         c.dm_idx = dm_idx;
         c.width_idx = width_idx;
@@ -629,7 +774,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
 
 // ------------------------------------------------------------------ host side
 struct Shape {
-  int pbw, cbp, pb, reg;
+  int pbw, cbp, pb, capb;  // capb: kept values per column workgroup (1/16 of its pixels)
 };
 
 template <int N>
@@ -637,7 +782,9 @@ Shape shape_n(const rf_plan *p) {
   Shape s;
   s.pbw = RowPairCfg<N>::PBW;
   s.cbp = N / ColCfg<N>::COLS;
-  s.reg = N * ColCfg<N>::COLS / 16;
+  s.capb = ColCfg<N>::COLS * N / 16;
+  static_assert(N / ColCfg<N>::COLS <= kMaxCB, "column workgroups per image");
+  static_assert(ColCfg<N>::COLS * N / 16 >= 128, "a list region holds the staged 128 values");
   // pairs per batch: keep the row-transformed batch (~128 MB) cache-resident
   const size_t per_pair = (size_t)std::max(1, p->n_rows) * N * sizeof(float2);
   const int pb = (int)std::max<size_t>(s.pbw, ((size_t)128 << 20) / per_pair);
@@ -684,7 +831,7 @@ Layout layout_of(const rf_plan *p) {
   for (int d = 0; d < 2; ++d) {
     L.epart[d] = take((size_t)sh.pb * std::max(1, p->n_rp) * 2 * sizeof(float));
     L.part[d] = take((size_t)2 * sh.pb * sh.cbp * sizeof(ColPart));
-    L.list[d] = take((size_t)2 * sh.pb * sh.cbp * sh.reg * sizeof(float));
+    L.list[d] = take((size_t)2 * sh.pb * sh.cbp * sh.capb * sizeof(float));
   }
   L.fb = take(((size_t)p->n_images + 1) * sizeof(int32_t));
   // buffers of the exact fallback (step chain on one image pair)
@@ -783,12 +930,11 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
   if (ov && ov->used[db]) RF_HIP_TRY(hipStreamWaitEvent(s, ov->sel_done[db], 0));
   const int npb = (pbn + sh.pbw - 1) / sh.pbw;
   const int nimg_b = std::min(2 * pbn, nimg_w - 2 * p0);  // images in this batch
-  const int bpi = (p->n_cells + kCellThreads - 1) / kCellThreads;
-  const int groups = (nimg_b + 7) / 8;
+  const int groups = (nimg_b + 8 * kCellImgs - 1) / (8 * kCellImgs);
   RF_TIMED(tm, RF_K_GRID,
-           (k_cellsum<<<(unsigned)(groups * 8 * bpi), kCellThreads, 0, s>>>(
-               vi, p->nbl * p->nchan, 2 * p0, nimg_b, p->n_cells, bpi, p->d_ucell_off,
-               p->d_contrib, cv)));
+           (k_cellsum<<<(unsigned)(groups * 8 * p->n_cblk), kCellThreads, 0, s>>>(
+               vi, p->nbl * p->nchan, 2 * p0, nimg_b, p->n_cells, p->n_cblk, p->d_cblk,
+               p->d_ucell_off, p->d_contrib, cv)));
   RF_TIMED(tm, RF_K_ROWS,
            (k_rows_pairs<N><<<(unsigned)(npb * p->n_rp), RowPairCfg<N>::NT, 0, s>>>(
                cv, p->n_cells, nimg_w, p0, pbn, p->d_rp_row, p->d_rp_sa, p->d_rp_sb, p->n_rp,
@@ -797,8 +943,8 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
   const float inv_w = 1.0f / (float)p->W;
   RF_TIMED(tm, RF_K_COLS,
            (k_cols_stats<N><<<(unsigned)(pbn * sh.cbp), ColCfg<N>::NT, 0, s>>>(
-               M, p->n_rows, p->d_row_slot, nimg_w, p0, pbn, inv_w, p->d_tw, epart, p->n_rp,
-               part, list, sh.reg)));
+               M, p->n_rows, p->vmax, nimg_w, p0, pbn, inv_w, p->d_tw, epart, p->n_rp,
+               part, list, sh.capb)));
   hipStream_t ss = s;
   if (ov) {
     RF_HIP_TRY(hipEventRecord(ov->cols_done[db], s));
@@ -807,7 +953,7 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
   }
   RF_TIMED(tm, RF_K_SELECT,
            (k_select<<<(unsigned)(2 * pbn), kSelThreads, 0, ss>>>(
-               part, list, sh.cbp, sh.reg, nimg_w, p0, pbn, N, dm_idx, width_idx, width,
+               part, list, sh.cbp, sh.capb, nimg_w, p0, pbn, N, dm_idx, width_idx, width,
                stat_base, stats, cand, cap, ncand, fb, fb + 1, p->threshold, p->t_begin,
                p->t_end)));
   if (ov) {

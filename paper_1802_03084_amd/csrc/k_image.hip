@@ -21,15 +21,13 @@ using namespace rf;
 template <int N>
 __global__ __launch_bounds__(RowCfg<N>::NT) void k_rows_dense(
     const float2 *__restrict__ grid, int nimg, const int32_t *__restrict__ rows, int n_rows,
-    int row_blocks, const float2 *__restrict__ tw_g, float2 *__restrict__ M) {
+    int row_blocks, const float2 *__restrict__ tw, float2 *__restrict__ M) {
   constexpr int F = RowCfg<N>::F, NT = RowCfg<N>::NT, S = RowCfg<N>::STRIDE;
-  constexpr int PS = FftShape<N>::PS;
+  constexpr int PS = FftPad<N>::PS;
   __shared__ float2 buf[F * S];
-  __shared__ float2 tw[N];
   const int pair = blockIdx.x / row_blocks;
   const int slot0 = (blockIdx.x % row_blocks) * F;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
   const size_t npix2 = (size_t)N * N;
   const float2 *Ga = grid + (size_t)(2 * pair) * npix2;
   const float2 *Gb = Ga + npix2;
@@ -53,39 +51,39 @@ __global__ __launch_bounds__(RowCfg<N>::NT) void k_rows_dense(
     buf[f * S + pidx<PS>(u)] = z;
   }
   __syncthreads();
-  fft_inverse<N, F, NT, S>(buf, tw, tid);
-  for (int e = tid; e < F * N; e += NT) {
-    const int f = e / N, x = e % N;
-    const int slot = slot0 + f;
-    if (slot < n_rows) M[((size_t)pair * n_rows + slot) * N + x] = buf[f * S + pidx<PS>(x)];
-  }
+  fft_inverse<N, F, NT, S, true>(
+      buf, tw, tid, [&](int f, int i) { return buf[f * S + pidx<PS>(i)]; },
+      [&](int f, int x, float2 v) {
+        const int slot = slot0 + f;
+        if (slot < n_rows) M[((size_t)pair * n_rows + slot) * N + x] = v;
+      });
 }
 
 template <int N>
 __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_image(
-    const float2 *__restrict__ M, int n_rows, const int32_t *__restrict__ row_slot, int nimg,
-    float inv_w, const float2 *__restrict__ tw_g, float *__restrict__ img) {
+    const float2 *__restrict__ M, int n_rows, int vmax, int nimg,
+    float inv_w, const float2 *__restrict__ tw, float *__restrict__ img) {
   constexpr int COLS = ColCfg<N>::COLS, NT = ColCfg<N>::NT, S = ColCfg<N>::STRIDE;
-  constexpr int PS = FftShape<N>::PS;
   constexpr int CB = N / COLS;
   __shared__ float2 buf[COLS * S];
-  __shared__ float2 tw[N];
   const int pair = blockIdx.x / CB;
   const int x0 = (blockIdx.x % CB) * COLS;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
-  load_col_tile<N>(M + (size_t)pair * n_rows * N + x0, row_slot, buf, tid);
-  __syncthreads();
-  fft_inverse<N, COLS, NT, S>(buf, tw, tid);
+  const float2 *Mp = M + (size_t)pair * n_rows * N + x0;
   float *ia = img + (size_t)(2 * pair) * N * N + x0;
   float *ib = ia + (size_t)N * N;
   const bool hasb = 2 * pair + 1 < nimg;
-  for (int e = tid; e < N * COLS; e += NT) {
-    const int y = e / COLS, x = e % COLS;
-    const float2 v = buf[x * S + pidx<PS>(y)];
-    ia[(size_t)y * N + x] = v.x * inv_w;
-    if (hasb) ib[(size_t)y * N + x] = v.y * inv_w;
-  }
+  fft_inverse<N, COLS, NT, S, false>(
+      buf, tw, tid,
+      [&](int f, int i) {  // branch-free: every load is issued before any is used
+        const int slot = band_slot(i, N, vmax);
+        const float2 m = Mp[(size_t)max(slot, 0) * N + f];
+        return slot >= 0 ? m : make_float2(0.f, 0.f);
+      },
+      [&](int f, int y, float2 v) {
+        ia[(size_t)y * N + f] = v.x * inv_w;
+        if (hasb) ib[(size_t)y * N + f] = v.y * inv_w;
+      });
 }
 
 template <int N>
@@ -101,7 +99,7 @@ rf_status image_dense_n(const rf_plan *p, const float2 *grid, int nimg, float *i
   RF_HIP_TRY(hipGetLastError());
   constexpr int CB = N / ColCfg<N>::COLS;
   k_cols_image<N><<<(unsigned)((size_t)CB * npairs), ColCfg<N>::NT, 0, s>>>(
-      ws, p->n_rows, p->d_row_slot, nimg, inv_w, p->d_tw, img);
+      ws, p->n_rows, p->vmax, nimg, inv_w, p->d_tw, img);
   RF_HIP_TRY(hipGetLastError());
   return RF_OK;
 }

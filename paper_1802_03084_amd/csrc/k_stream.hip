@@ -32,12 +32,18 @@ __global__ __launch_bounds__(kThreads) void k_dedisperse(const E *__restrict__ i
   const size_t plane = (size_t)nbc;
   E zero;
   __builtin_memset(&zero, 0, sizeof(E));
-#pragma unroll 4
-  for (int t = t0; t < t1; ++t) {
-    const int src = t + d;
-    E v = zero;
-    if (src < nint) v = in[(size_t)src * plane + bc];
-    out[(size_t)t * plane + bc] = v;
+  constexpr int U = 8;  // loads in flight per thread
+  for (int tb = t0; tb < t1; tb += U) {
+    E v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {  // branch-free: clamp the address, zero the value
+      const int src = tb + u + d;
+      const E x = in[(size_t)min(src, nint - 1) * plane + bc];
+      v[u] = src < nint ? x : zero;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (tb + u < t1) out[(size_t)(tb + u) * plane + bc] = v[u];
   }
 }
 

@@ -23,7 +23,7 @@ bool finite(double x) { return std::isfinite(x); }
 
 struct TableLayout {
   size_t freq, uvw, dm, delay, cells, contrib, ucell, ucell_off, rows, row_slot, tw;
-  size_t rp_row, rp_sa, rp_sb, zs_off, zs_u, zs_ck, zs_cmk, total;
+  size_t rp_row, rp_sa, rp_sb, zs_off, zs_u, zs_ck, zs_cmk, cblk, total;
 };
 
 TableLayout table_layout(const rf_plan_desc *d) {
@@ -53,6 +53,7 @@ TableLayout table_layout(const rf_plan_desc *d) {
   L.zs_u = take(sizeof(int32_t) * 2 * bc);
   L.zs_ck = take(sizeof(int32_t) * 2 * bc);
   L.zs_cmk = take(sizeof(int32_t) * 2 * bc);
+  L.cblk = take(sizeof(int32_t) * (bc + 2));
   L.total = o;
   return L;
 }
@@ -170,6 +171,7 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
   p->d_zs_u = (int32_t *)(base + L.zs_u);
   p->d_zs_ck = (int32_t *)(base + L.zs_ck);
   p->d_zs_cmk = (int32_t *)(base + L.zs_cmk);
+  p->d_cblk = (int32_t *)(base + L.cblk);
 
   RF_HIP_TRY(hipMemcpyAsync(d_freq, p->freq.data(), sizeof(double) * d->nchan,
                             hipMemcpyHostToDevice, s));
@@ -214,9 +216,17 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
   }
   off.push_back((int32_t)kv.size());
   p->n_cells = (int32_t)ucell.size();
+  // Stored rows: the band |v| <= vmax of the Hermitian-symmetrised grid,
+  // v = 0..vmax then v = N-vmax..N-1, so that a row's slot is a closed form
+  // (row r -> r, or r - (N - 2 vmax - 1)); empty rows inside the band are
+  // transformed as zeros.
+  int vmax = -1;
+  for (int r = 0; r < N; ++r)
+    if (occ[r]) vmax = std::max(vmax, std::min(r, N - r));
+  p->vmax = vmax;
   std::vector<int32_t> rows, row_slot(N, -1);
   for (int r = 0; r < N; ++r)
-    if (occ[r] || occ[(N - r) & (N - 1)]) {
+    if (std::min(r, N - r) <= vmax) {
       row_slot[r] = (int32_t)rows.size();
       rows.push_back(r);
     }
@@ -258,6 +268,16 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
     zs_off.push_back((int32_t)zs_u.size());
   }
   p->n_rp = (int32_t)rp_row.size();
+  // cell blocks of at most 1024 contributors for the staged gather
+  std::vector<int32_t> cblk;
+  for (int32_t c = 0; c < p->n_cells;) {
+    cblk.push_back(c);
+    int32_t e = c + 1;
+    while (e < p->n_cells && off[e + 1] - off[c] <= 1024 && e - c < 1024) ++e;
+    c = e;
+  }
+  cblk.push_back(p->n_cells);
+  p->n_cblk = (int32_t)cblk.size() - 1;
   p->n_zs = (int32_t)zs_u.size();
 
   if (!contrib.empty())
@@ -282,6 +302,8 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
     RF_HIP_TRY(hipMemcpyAsync(p->d_rp_sa, rp_sa.data(), rb, hipMemcpyHostToDevice, s));
     RF_HIP_TRY(hipMemcpyAsync(p->d_rp_sb, rp_sb.data(), rb, hipMemcpyHostToDevice, s));
   }
+  RF_HIP_TRY(hipMemcpyAsync(p->d_cblk, cblk.data(), sizeof(int32_t) * cblk.size(),
+                            hipMemcpyHostToDevice, s));
   if (p->n_zs > 0) {
     const size_t zb = sizeof(int32_t) * p->n_zs;
     RF_HIP_TRY(hipMemcpyAsync(p->d_zs_u, zs_u.data(), zb, hipMemcpyHostToDevice, s));

@@ -23,7 +23,8 @@ struct rf_plan {
   int32_t W;          // valid (baseline, channel) pairs
   int32_t n_dropped;
   int32_t n_cells;    // distinct occupied cells
-  int32_t n_rows;     // occupied rows of the Hermitian-symmetrised grid
+  int32_t n_rows;     // stored rows: the band |v| <= vmax (2 vmax + 1 rows)
+  int32_t vmax;       // largest |v| of a gridded sample (-1 if none)
   int32_t max_delay;
   int64_t n_images;
   size_t table_bytes;
@@ -36,7 +37,7 @@ struct rf_plan {
   int32_t *d_ucell;         // [n_cells] linear cell (iv mod N) * N + (iu mod N), ascending
   int32_t *d_ucell_off;     // [n_cells + 1] CSR offsets into d_contrib
   int32_t *d_rows;          // [n_rows] occupied rows, ascending
-  int32_t *d_row_slot;      // [N] compact slot of a row in d_rows, or -1
+  int32_t *d_row_slot;      // [N] compact slot of a row in d_rows, or -1 (= band_slot)
   float2 *d_tw;             // [N] exp(+2 pi i m / N)
   // Z positions of the paired Hermitian transform, grouped by row pair
   // {v, -v} (v in [0, N/2], occupied): row pair rp has rows v = rp_row[rp]
@@ -45,6 +46,10 @@ struct rf_plan {
   // index (into d_ucell) at (v, u) and zs_cmk the one at (-v, -u), -1 where
   // the grid is empty.  Row -v's positions are the mirrors (-u).
   int32_t n_rp, n_zs;
+  // cell blocks for the staged gather: block b is cells cblk[b] .. cblk[b+1]-1,
+  // at most 1024 contributors (a single heavier cell forms its own block)
+  int32_t n_cblk;
+  int32_t *d_cblk;          // [n_cblk + 1]
   int32_t *d_rp_row;        // [n_rp]
   int32_t *d_rp_sa;         // [n_rp]
   int32_t *d_rp_sb;         // [n_rp]
@@ -57,6 +62,11 @@ struct rf_plan {
   std::vector<int32_t> h_delay;
   std::vector<int32_t> h_cells;
 };
+
+// Slot of grid row r in the stored band |v| <= vmax, or -1 outside it.
+__host__ __device__ inline int band_slot(int r, int N, int vmax) {
+  return r <= vmax ? r : (r >= N - vmax ? r - (N - 2 * vmax - 1) : -1);
+}
 
 #define RF_HIP_TRY(expr)                      \
   do {                                        \

@@ -1,0 +1,169 @@
+"""Parity at full survey size and at the other workload shapes, through the
+C ABI in the configuration bench.py times (rf_search_segment, fused path).
+
+At full size the oracle recomputes sampled images one by one (float64);
+candidate keys of the injected pulses must be exact and the sampled images'
+peak, position and sigma within the image bar.  Other workload shapes (the
+2048^2 large-image shape, the 512^2 serving shape with L-band subarrays,
+1024 channels) run with few integrations so the oracle can image all of
+them.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import rfgen
+from helpers import cand_keys, gpu_plan, oracle_plan, upload
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL16 = 3e-3
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def survey_data():
+    p = rfgen.survey()
+    say("generating the survey segment")
+    return p, p.make_vis()
+
+
+def _sampled_keys(p):
+    keys = set()
+    for q in p.pulses:
+        keys.add((q.dm_idx, q.width_idx, q.t0 // p.widths[q.width_idx]))
+    rng = np.random.default_rng(77)
+    for _ in range(8):
+        i = int(rng.integers(0, len(p.dms)))
+        j = int(rng.integers(0, len(p.widths)))
+        k = int(rng.integers(0, p.nint // p.widths[j]))
+        keys.add((i, j, k))
+    keys.add((len(p.dms) - 1, 0, p.nint - 1))   # most zero-filled image
+    keys.add((0, len(p.widths) - 1, p.nint // p.widths[-1] - 1))
+    return sorted(keys)
+
+
+@pytest.mark.parametrize("dtype,tol", [(0, TOL32), (1, TOL16)])
+def test_survey_full_size(torch, survey_data, dtype, tol):
+    p, vis = survey_data
+    say("survey full size, storage", dtype)
+    g = gpu_plan(p, vis_dtype=dtype)
+    o = oracle_plan(p)
+    dv = upload(vis, dtype)
+    rows, n, st = g.search_segment(dv, cap=65536, with_stats=True)
+    assert n == len(rows)
+    keys = cand_keys(rows)
+    for q in p.pulses:
+        assert (q.dm_idx, q.width_idx, q.t0, q.x, q.y) in keys, q
+    del dv
+    torch.cuda.empty_cache()
+    for (i, j, k) in _sampled_keys(p):
+        img = oracle.image_at(vis, o, i, j, k)
+        peak, x, y, sigma, snr = oracle.image_stats(img)
+        s = st[g.image_base(i, j) + k]
+        amax = float(np.max(np.abs(img)))
+        marginal = oracle.is_marginal(img, snr, o.threshold, tol)
+        if not marginal:
+            assert (int(s["x"]), int(s["y"])) == (x, y), (i, j, k)
+            assert (snr > o.threshold) == (float(s["snr"]) > o.threshold), (i, j, k)
+        assert abs(float(s["peak"]) - peak) <= tol * amax, (i, j, k)
+        assert abs(float(s["sigma"]) - sigma) <= 1.4826 * tol * amax, (i, j, k)
+
+
+def _few_ints(p, nint):
+    p.nint = nint
+    p.t_end = nint
+    p.pulses = [q for q in p.pulses if q.t0 + 2 * p.widths[q.width_idx] <= nint]
+    return p
+
+
+def _shape_parity(p, dtype=0, tol=TOL32):
+    o = oracle_plan(p)
+    g = gpu_plan(p, vis_dtype=dtype)
+    vis = p.make_vis()
+    rows, n, st = g.search_segment(upload(vis, dtype), cap=4096, with_stats=True)
+    ostats, ocands, oimgs = oracle.search(vis, o, keep_images=True)
+    marginal = set()
+    for key, ref in ostats.items():
+        i, j, k = key
+        s = st[g.image_base(i, j) + k]
+        peak, x, y, sigma, snr = ref
+        amax = float(np.max(np.abs(oimgs[key])))
+        if oracle.is_marginal(oimgs[key], snr, o.threshold, tol):
+            marginal.add(key)
+        else:
+            assert (int(s["x"]), int(s["y"])) == (x, y), key
+        assert abs(float(s["peak"]) - peak) <= tol * amax, key
+        assert abs(float(s["sigma"]) - sigma) <= 1.4826 * tol * amax, key
+    want = [c[:5] for c in ocands if (c[0], c[1], c[2] // p.widths[c[1]]) not in marginal]
+    got = [kk for kk in cand_keys(rows) if (kk[0], kk[1], kk[2] // p.widths[kk[1]]) not in marginal]
+    assert got == want
+    return rows
+
+
+def test_large_image_shape(torch):
+    """2048^2 images, 1024 channels over 2-4 GHz, 1 ms integrations."""
+    n = 2048
+    p = rfgen.Preset(name="large-shape", nant=27, nint=6, tint_s=0.001, f_lo_ghz=2.0, f_hi_ghz=4.0,
+                     nchan=1024, npol=2, dms=np.array([0.0, 30.0]), widths=[1, 2], npix=n, seed=4,
+                     pulses=[rfgen.Pulse(dm_idx=0, width_idx=0, t0=2, x=n // 2 + 40, y=n // 2 - 30)])
+    say("large-image shape")
+    rows = _shape_parity(p)
+    assert (0, 0, 2, n // 2 + 40, n // 2 - 30) in cand_keys(rows)
+
+
+@pytest.mark.parametrize("nant,tint", [(10, 0.005), (19, 0.010), (27, 0.005)])
+def test_serving_subarray_shapes(torch, nant, tint):
+    """512^2 images, 256 channels over the L band of Table 1 (1.272-1.528 GHz)."""
+    p = rfgen.Preset(name="serving-shape", nant=nant, nint=12, tint_s=tint, f_lo_ghz=1.272,
+                     f_hi_ghz=1.528, nchan=256, npol=2, dms=np.linspace(0, 1000, 3),
+                     widths=[1, 2, 4], npix=512, seed=3 + nant,
+                     pulses=[rfgen.Pulse(dm_idx=0, width_idx=1, t0=4, x=270, y=240)])
+    say("serving shape", nant, tint)
+    rows = _shape_parity(p)
+    assert (0, 1, 4, 270, 240) in cand_keys(rows)
+
+
+def test_all_zero_segment(torch):
+    """Identically zero data: every image is zero, sigma 0, S/N 0, no candidate."""
+    p = rfgen.smallcase()
+    say("all-zero segment")
+    g = gpu_plan(p)
+    vis = np.zeros((p.nint, p.nbl, p.nchan, p.npol), np.complex64)
+    rows, n, st = g.search_segment(upload(vis), cap=64, with_stats=True)
+    assert n == 0
+    assert (st["sigma"] == 0).all() and (st["snr"] == 0).all() and (st["peak"] == 0).all()
+
+
+def test_single_polarisation_segment(torch):
+    p = rfgen.smallcase(npol=1, nint=20, npix=256, seed=12)
+    say("single polarisation")
+    _shape_parity(p)
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_noise_images_take_no_fallback(torch, n):
+    """Noise images keep their median inside the bracket: every image is
+    finished by the fused select, none by the exact recomputation."""
+    p = rfgen.Preset(name="noise", nant=27, nint=16, tint_s=0.005, f_lo_ghz=1.0, f_hi_ghz=2.0,
+                     nchan=256, npol=2, dms=np.array([0.0, 300.0]), widths=[1, 2], npix=n,
+                     seed=21, pulses=[])
+    say("noise-only fallback count", n)
+    g = gpu_plan(p)
+    times, rows, ncand = g.profile_segment(upload(p.make_vis()))
+    assert times["fallback"][1] == 0, times
+    assert times["select"][1] > 0
