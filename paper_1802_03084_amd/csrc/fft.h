@@ -8,12 +8,12 @@
 //   y[(j / NS) NS R + (j mod NS) + r NS] = v[r]
 // which is the classical self-sorting Stockham formulation of the radix-R
 // Cooley-Tukey FFT: after the last pass y is the inverse DFT in natural
-// order.  N is split into two passes (three for N = 2048) of radix up to 32
-// held in registers: the first pass reads its inputs from wherever the
-// caller keeps them (global memory for the column transform), the passes
-// exchange through one padded LDS buffer, and the last pass hands its
-// outputs to the caller in registers.  Twiddles come from a global table
-// tw[m] = exp(+2 pi i m / N) computed on the host in float64.
+// order.  A shape type fixes the radices (two or three passes held in
+// registers): the first pass reads its inputs from wherever the caller keeps
+// them (global memory for the column transform), the passes exchange through
+// one padded LDS buffer, and the last pass hands its outputs to the caller in
+// registers.  Twiddles come from a global table tw[m] = exp(+2 pi i m / N)
+// computed on the host in float64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -127,20 +127,35 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
 template <int PS>
 __device__ __forceinline__ int pidx(int i) { return i + (i >> PS); }
 
-// Radix schedule (two or three passes) and LDS padding for each N.
-template <int N>
-struct FftShape;
-template <> struct FftShape<64> { static constexpr int R0 = 8, R1 = 8, R2 = 1; };
-template <> struct FftShape<128> { static constexpr int R0 = 16, R1 = 8, R2 = 1; };
-template <> struct FftShape<256> { static constexpr int R0 = 16, R1 = 16, R2 = 1; };
-template <> struct FftShape<512> { static constexpr int R0 = 32, R1 = 16, R2 = 1; };
-template <> struct FftShape<1024> { static constexpr int R0 = 32, R1 = 32, R2 = 1; };
-template <> struct FftShape<2048> { static constexpr int R0 = 32, R1 = 8, R2 = 8; };
-template <int N>
-struct FftPad {
-  static constexpr int PS = FftShape<N>::R0 == 32 ? 5 : (FftShape<N>::R0 == 16 ? 4 : 3);
-  static constexpr int PADDED = N + (N >> PS);   // padded length of one sequence
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
+// Radix schedule of a length-N transform: R0 R1 R2 = N, R2 = 1 for two
+// passes.  PADDED is the padded LDS length of one sequence.
+template <int N_, int R0_, int R1_, int R2_>
+struct FftShape {
+  static constexpr int N = N_, R0 = R0_, R1 = R1_, R2 = R2_;
+  static_assert(R0 * R1 * R2 == N, "radices multiply to N");
+  static constexpr int PS = ilog2(R0);
+  static constexpr int PADDED = N + (N >> PS);
 };
+
+// Row transforms (along u): two register passes of radix up to 32 (three at
+// 2048).  Column transforms (along v): passes of radix up to 16, so that a
+// thread holds 16 values and four waves per SIMD fit in the register file.
+template <int N> struct RowFft;
+template <> struct RowFft<64> : FftShape<64, 8, 8, 1> {};
+template <> struct RowFft<128> : FftShape<128, 16, 8, 1> {};
+template <> struct RowFft<256> : FftShape<256, 16, 16, 1> {};
+template <> struct RowFft<512> : FftShape<512, 32, 16, 1> {};
+template <> struct RowFft<1024> : FftShape<1024, 32, 32, 1> {};
+template <> struct RowFft<2048> : FftShape<2048, 32, 8, 8> {};
+template <int N> struct ColFft;
+template <> struct ColFft<64> : FftShape<64, 8, 8, 1> {};
+template <> struct ColFft<128> : FftShape<128, 16, 8, 1> {};
+template <> struct ColFft<256> : FftShape<256, 16, 16, 1> {};
+template <> struct ColFft<512> : FftShape<512, 8, 8, 8> {};
+template <> struct ColFft<1024> : FftShape<1024, 16, 8, 8> {};
+template <> struct ColFft<2048> : FftShape<2048, 16, 16, 8> {};
 
 // Butterfly index -> (sequence f, butterfly j).  JF: j fastest across
 // threads (rows: contiguous along the transform); otherwise f fastest
@@ -156,58 +171,102 @@ __device__ __forceinline__ void fj_of(int idx, int &f, int &j) {
   }
 }
 
-// First pass (no twiddles): inputs from load(f, i) (global memory or LDS),
-// radix-R0 DFT, results to LDS at the Stockham position j R0 + r.
-template <int N, int F, int NT, int S, bool JF, class Load>
-__device__ __forceinline__ void fft_first(float2 *buf, int tid, Load load) {
-  constexpr int R = FftShape<N>::R0, NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT;
-  constexpr int PS = FftPad<N>::PS;
+// First pass (no twiddles): inputs from load(f, i), radix-R0 DFT, results to
+// LDS at the Stockham position j R0 + r.  The pass comes in three parts
+// (fft_first_load: the inputs into registers; fft_first_dft; fft_first_store:
+// the LDS write) so that a caller can do other work while the loads are in
+// flight.
+template <class Sh, int F, int NT>
+struct FirstRegs {
+  static constexpr int R = Sh::R0, NB = Sh::N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT;
   float2 v[Q][R];
+};
+
+template <class Sh, int F, int NT, bool JF, class Load>
+__device__ __forceinline__ void fft_first_load(int tid, Load load, FirstRegs<Sh, F, NT> &x) {
+  using X = FirstRegs<Sh, F, NT>;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
+  for (int q = 0; q < X::Q; ++q) {
     const int idx = tid + q * NT;
-    if ((TOT % NT) == 0 || idx < TOT) {
+    if ((X::TOT % NT) == 0 || idx < X::TOT) {
       int f, j;
-      fj_of<F, NB, JF>(idx, f, j);
+      fj_of<F, X::NB, JF>(idx, f, j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = load(f, j + r * NB);
+      for (int r = 0; r < X::R; ++r) x.v[q][r] = load(f, j + r * X::NB);
     }
   }
+}
+
+template <class Sh, int F, int NT>
+__device__ __forceinline__ void fft_first_dft(FirstRegs<Sh, F, NT> &x) {
+  using X = FirstRegs<Sh, F, NT>;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) dft<R>(v[q]);
+  for (int q = 0; q < X::Q; ++q) dft<X::R>(x.v[q]);
+}
+
+// LDS write of the first pass; the caller synchronises before it (if buf is
+// still being read) and after.  With PRE, each output is first multiplied by
+// the twiddle that the second pass would apply to it when gathering (same
+// operands, same operation: bit-identical), and the second pass must then
+// run with its twiddles off.
+template <class Sh, int F, int NT, int S, bool JF, bool PRE = false>
+__device__ __forceinline__ void fft_first_store(float2 *buf, const float2 *__restrict__ tw, int tid,
+                                                FirstRegs<Sh, F, NT> &x) {
+  using X = FirstRegs<Sh, F, NT>;
+  constexpr int N = Sh::N, PS = Sh::PS;
+  constexpr int NB1 = N / Sh::R1, NS1 = Sh::R0, TS1 = N / (Sh::R0 * Sh::R1);
+#pragma unroll
+  for (int q = 0; q < X::Q; ++q) {
+    const int idx = tid + q * NT;
+    if ((X::TOT % NT) == 0 || idx < X::TOT) {
+      int f, j;
+      fj_of<F, X::NB, JF>(idx, f, j);
+#pragma unroll
+      for (int r = 0; r < X::R; ++r) {
+        const int p = j * X::R + r;  // the second pass reads it as element p / NB1 of butterfly p % NB1
+        if constexpr (PRE) {
+          const int r1 = p / NB1, jm = (p % NB1) % NS1;
+          x.v[q][r] = cmul(x.v[q][r], tw[jm * r1 * TS1]);
+        }
+        buf[f * S + pidx<PS>(p)] = x.v[q][r];
+      }
+    }
+  }
+}
+
+template <class Sh, int F, int NT, int S, bool JF, class Load>
+__device__ __forceinline__ void fft_first(float2 *buf, int tid, Load load) {
+  FirstRegs<Sh, F, NT> x;
+  fft_first_load<Sh, F, NT, JF>(tid, load, x);
+  __builtin_amdgcn_sched_barrier(0);  // every load issued before the transform starts
+  fft_first_dft<Sh, F, NT>(x);
   __syncthreads();  // inputs may have come from buf
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int idx = tid + q * NT;
-    if ((TOT % NT) == 0 || idx < TOT) {
-      int f, j;
-      fj_of<F, NB, JF>(idx, f, j);
-#pragma unroll
-      for (int r = 0; r < R; ++r) buf[f * S + pidx<PS>(j * R + r)] = v[q][r];
-    }
-  }
+  fft_first_store<Sh, F, NT, S, JF>(buf, nullptr, tid, x);
   __syncthreads();
 }
 
 // Loads butterfly (f, j) of a radix-R pass from LDS and applies the twiddles
 // w^(r (j mod NS)), w = exp(+2 pi i / (NS R)), from the global table
-// tw[m] = exp(+2 pi i m / N).
-template <int N, int R, int NS, int S, int PS>
+// tw[m] = exp(+2 pi i m / N).  Every element is multiplied, r = 0 included
+// (by tw[0] = 1, exact up to the sign of a zero), so that no load sits
+// behind a branch.
+template <int N, int R, int NS, int S, int PS, bool TW = true>
 __device__ __forceinline__ void fft_gather(const float2 *buf, const float2 *__restrict__ tw, int f,
                                            int j, float2 (&v)[R]) {
   constexpr int NB = N / R;
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = buf[f * S + pidx<PS>(j + r * NB)];
-  const int jm = j % NS;
+  if constexpr (TW) {
+    const int jm = j % NS;
 #pragma unroll
-  for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[jm * r * (N / (NS * R))]);
+    for (int r = 0; r < R; ++r) v[r] = cmul(v[r], tw[jm * r * (N / (NS * R))]);
+  }
 }
 
 // Middle pass: LDS -> LDS in place.
-template <int N, int R, int NS, int F, int NT, int S, bool JF>
+template <class Sh, int R, int NS, int F, int NT, int S, bool JF, bool TW = true>
 __device__ __forceinline__ void fft_mid(float2 *buf, const float2 *__restrict__ tw, int tid) {
-  constexpr int NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT;
-  constexpr int PS = FftPad<N>::PS;
+  constexpr int N = Sh::N, NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT, PS = Sh::PS;
   float2 v[Q][R];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -215,7 +274,7 @@ __device__ __forceinline__ void fft_mid(float2 *buf, const float2 *__restrict__ 
     if ((TOT % NT) == 0 || idx < TOT) {
       int f, j;
       fj_of<F, NB, JF>(idx, f, j);
-      fft_gather<N, R, NS, S, PS>(buf, tw, f, j, v[q]);
+      fft_gather<N, R, NS, S, PS, TW>(buf, tw, f, j, v[q]);
       dft<R>(v[q]);
     }
   }
@@ -236,11 +295,10 @@ __device__ __forceinline__ void fft_mid(float2 *buf, const float2 *__restrict__ 
 
 // Last pass: LDS -> registers, results handed to store(f, k, value) with k the
 // natural-order output index.
-template <int N, int R, int NS, int F, int NT, int S, bool JF, class Store>
+template <class Sh, int R, int NS, int F, int NT, int S, bool JF, bool TW, class Store>
 __device__ __forceinline__ void fft_last(const float2 *buf, const float2 *__restrict__ tw, int tid,
                                          Store store) {
-  constexpr int NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT;
-  constexpr int PS = FftPad<N>::PS;
+  constexpr int N = Sh::N, NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT, PS = Sh::PS;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int idx = tid + q * NT;
@@ -248,7 +306,7 @@ __device__ __forceinline__ void fft_last(const float2 *buf, const float2 *__rest
       int f, j;
       fj_of<F, NB, JF>(idx, f, j);
       float2 v[R];
-      fft_gather<N, R, NS, S, PS>(buf, tw, f, j, v);
+      fft_gather<N, R, NS, S, PS, TW>(buf, tw, f, j, v);
       dft<R>(v);
       const int d0 = (j / NS) * NS * R + (j % NS);
 #pragma unroll
@@ -259,11 +317,10 @@ __device__ __forceinline__ void fft_last(const float2 *buf, const float2 *__rest
 
 // Last pass variant: consume(f, k0, kstep, v) receives a butterfly's R outputs
 // at natural-order indices k0 + r * kstep in increasing r (kstep = NS).
-template <int N, int R, int NS, int F, int NT, int S, bool JF, class Consume>
+template <class Sh, int R, int NS, int F, int NT, int S, bool JF, bool TW, class Consume>
 __device__ __forceinline__ void fft_last_block(const float2 *buf, const float2 *__restrict__ tw,
                                                int tid, Consume consume) {
-  constexpr int NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT;
-  constexpr int PS = FftPad<N>::PS;
+  constexpr int N = Sh::N, NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT, PS = Sh::PS;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int idx = tid + q * NT;
@@ -271,40 +328,39 @@ __device__ __forceinline__ void fft_last_block(const float2 *buf, const float2 *
       int f, j;
       fj_of<F, NB, JF>(idx, f, j);
       float2 v[R];
-      fft_gather<N, R, NS, S, PS>(buf, tw, f, j, v);
+      fft_gather<N, R, NS, S, PS, TW>(buf, tw, f, j, v);
       dft<R>(v);
       consume(f, (j / NS) * NS * R + (j % NS), NS, v);
     }
   }
 }
 
-// As fft_inverse, with the last pass handing whole butterflies to consume().
-template <int N, int F, int NT, int S, bool JF, class Load, class Consume>
-__device__ __forceinline__ void fft_inverse_blocks(float2 *buf, const float2 *__restrict__ tw,
-                                                   int tid, Load load, Consume consume) {
-  using Sh = FftShape<N>;
-  fft_first<N, F, NT, S, JF>(buf, tid, load);
+// The passes after the first (buf holds the first pass's output, written
+// with fft_first_store<..., PRE> and synchronised); the last pass hands whole
+// butterflies to consume.
+template <class Sh, int F, int NT, int S, bool JF, bool PRE, class Consume>
+__device__ __forceinline__ void fft_rest_blocks(float2 *buf, const float2 *__restrict__ tw,
+                                                int tid, Consume consume) {
   if constexpr (Sh::R2 == 1) {
-    fft_last_block<N, Sh::R1, Sh::R0, F, NT, S, JF>(buf, tw, tid, consume);
+    fft_last_block<Sh, Sh::R1, Sh::R0, F, NT, S, JF, !PRE>(buf, tw, tid, consume);
   } else {
-    fft_mid<N, Sh::R1, Sh::R0, F, NT, S, JF>(buf, tw, tid);
-    fft_last_block<N, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF>(buf, tw, tid, consume);
+    fft_mid<Sh, Sh::R1, Sh::R0, F, NT, S, JF, !PRE>(buf, tw, tid);
+    fft_last_block<Sh, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF, true>(buf, tw, tid, consume);
   }
 }
 
 // Inverse (exp(+i)) unnormalised FFT of F sequences of length N: inputs from
 // load(f, i), outputs to store(f, k, value), LDS buf of F * S elements
-// (S >= FftPad<N>::PADDED) for the exchanges between passes.
-template <int N, int F, int NT, int S, bool JF, class Load, class Store>
+// (S >= Sh::PADDED) for the exchanges between passes.
+template <class Sh, int F, int NT, int S, bool JF, class Load, class Store>
 __device__ __forceinline__ void fft_inverse(float2 *buf, const float2 *__restrict__ tw, int tid,
                                             Load load, Store store) {
-  using Sh = FftShape<N>;
-  fft_first<N, F, NT, S, JF>(buf, tid, load);
+  fft_first<Sh, F, NT, S, JF>(buf, tid, load);
   if constexpr (Sh::R2 == 1) {
-    fft_last<N, Sh::R1, Sh::R0, F, NT, S, JF>(buf, tw, tid, store);
+    fft_last<Sh, Sh::R1, Sh::R0, F, NT, S, JF, true>(buf, tw, tid, store);
   } else {
-    fft_mid<N, Sh::R1, Sh::R0, F, NT, S, JF>(buf, tw, tid);
-    fft_last<N, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF>(buf, tw, tid, store);
+    fft_mid<Sh, Sh::R1, Sh::R0, F, NT, S, JF>(buf, tw, tid);
+    fft_last<Sh, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF, true>(buf, tw, tid, store);
   }
 }
 
@@ -320,18 +376,36 @@ __device__ __forceinline__ float2 zval(float2 a, float2 am, float2 b, float2 bm,
   return make_float2(x, y);
 }
 
+// Raw buffer access: a load at an offset at or past the resource's size
+// returns zero (the hardware range check), so a load is switched off by its
+// offset alone and issued unconditionally, with no branch around it.
+constexpr uint32_t kNoLoad = 0x7ffffff0u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ float2 buf_load_f2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+  return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+__device__ __forceinline__ float buf_load_f1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+
 // Launch shapes of the two imaging passes for image side N.
 template <int N>
 struct RowCfg {  // dense rows: F grid rows per workgroup
   static constexpr int NT = 512;
   static constexpr int F = (8192 / N) < 64 ? (8192 / N) : 64;
-  static constexpr int STRIDE = FftPad<N>::PADDED;
+  static constexpr int STRIDE = RowFft<N>::PADDED;
 };
 template <int N>
-struct ColCfg {  // columns: COLS columns per workgroup (~68 KB LDS: two workgroups per CU)
+struct ColCfg {  // columns: COLS columns per workgroup (~70 KB LDS: two workgroups per CU)
   static constexpr int COLS = N >= 2048 ? 4 : (N >= 1024 ? 8 : (N >= 512 ? 16 : 32 < N ? 32 : N));
-  static constexpr int NT = COLS * N / FftShape<N>::R0 < 256 ? 256 : COLS * N / FftShape<N>::R0;
-  static constexpr int STRIDE = FftPad<N>::PADDED + 1;  // odd: neighbouring columns on other banks
+  static constexpr int FIRST = COLS * N / ColFft<N>::R0;  // first-pass butterflies
+  static constexpr int NT = N >= 512 ? 512 : (FIRST < 256 ? 256 : FIRST);
+  static constexpr int STRIDE = ColFft<N>::PADDED + 1;  // odd: neighbouring columns on other banks
 };
 
 }  // namespace rf

@@ -252,8 +252,8 @@ template <int N>
 struct RowPairCfg {
   static constexpr int PBW = N >= 2048 ? 2 : 4;  // image pairs per workgroup (~68 KB LDS)
   static constexpr int F = 2 * PBW;              // transforms per workgroup
-  static constexpr int NT = F * N / FftShape<N>::R0 < 256 ? 256 : F * N / FftShape<N>::R0;
-  static constexpr int STRIDE = FftPad<N>::PADDED;
+  static constexpr int NT = F * N / RowFft<N>::R0 < 256 ? 256 : F * N / RowFft<N>::R0;
+  static constexpr int STRIDE = RowFft<N>::PADDED;
 };
 
 template <int N>
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
     const int32_t *__restrict__ zs_cmk, const float2 *__restrict__ tw, float2 *__restrict__ M,
     float *__restrict__ epart) {
   constexpr int PBW = RowPairCfg<N>::PBW, F = RowPairCfg<N>::F, NT = RowPairCfg<N>::NT;
-  constexpr int S = RowPairCfg<N>::STRIDE, PS = FftPad<N>::PS;
+  constexpr int S = RowPairCfg<N>::STRIDE, PS = RowFft<N>::PS;
   __shared__ float2 buf[F * S];
   __shared__ float s_e[2 * PBW];
   const int rp = blockIdx.x % n_rp;
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
   if (tid < 2 * PBW && pb0 + tid / 2 < pbn)
     epart[((size_t)(pb0 + tid / 2) * n_rp + rp) * 2 + (tid & 1)] = s_e[tid];
   const int sa = rp_sa[rp], sb = rp_sb[rp];
-  fft_inverse<N, F, NT, S, true>(
+  fft_inverse<RowFft<N>, F, NT, S, true>(
       buf, tw, tid, [&](int f, int i) { return buf[f * S + pidx<PS>(i)]; },
       [&](int f, int x, float2 v) {
         const int side = f / PBW, pp = f % PBW;
@@ -319,116 +319,148 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
 }
 
 // ------------------------------------------------------------------ columns
+// Column pass and per-image statistics.  A workgroup takes a tile of COLS
+// adjacent columns of one image pair.  Workgroups are dealt to the eight XCDs
+// round robin (b mod 8); XCD x takes a contiguous run of tiles, so the column
+// tiles that run together on one XCD are adjacent and share their cache
+// lines in that XCD's L2.  All global loads (the tile and the pair's energy
+// terms) are issued together, without branches, before any is used.
+//
+// Per tile and image: the peak (signed max, lowest flat index on ties), the
+// count of |pixel| below the median bracket, and the bracket values
+// themselves (into this tile's list region of capb values; the count may
+// exceed capb, which sends the image to the exact fallback).  The bracket is
+// kMedOverRms * rms (1 +- bracket_of<N>()), with the rms from Parseval: the
+// image energy is the grid energy (summed by the row pass) over N^2 W^2.
 template <int N>
 __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
     const float2 *__restrict__ M, int n_rows, int vmax, int nimg_w,
     int p0, int pbn, float inv_w, const float2 *__restrict__ tw, const float *__restrict__ epart,
     int n_rp, ColPart *__restrict__ part, float *__restrict__ list, int capb) {
+  using Sh = ColFft<N>;
   constexpr int COLS = ColCfg<N>::COLS, NT = ColCfg<N>::NT, S = ColCfg<N>::STRIDE;
   constexpr int CB = N / COLS;
   constexpr int NW = NT / 64;
+  constexpr int EPT = ((N / 2 + 1) * 2 + NT - 1) / NT;  // energy terms per thread, at most
+  static_assert(NT % 2 == 0, "energy terms alternate a, b by thread parity");
   __shared__ float2 buf[COLS * S];
-  __shared__ float s_br[4];
+  __shared__ float s_e[2][NW];
   __shared__ uint32_t s_cnt[2];
   __shared__ float w_v[2][NW];
   __shared__ int32_t w_i[2][NW];
   __shared__ uint32_t w_c[2][NW];
-  const int pl = blockIdx.x / CB;
-  const int cb = blockIdx.x % CB;
-  if (pl >= pbn) return;
-  const int tid = threadIdx.x;
-  const int x0 = cb * COLS;
-  if (tid < 64) {
-    float ea = 0.f, eb = 0.f;
-    for (int r = tid; r < n_rp; r += 64) {
-      ea += epart[2 * ((size_t)pl * n_rp + r) + 0];
-      eb += epart[2 * ((size_t)pl * n_rp + r) + 1];
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      ea += __shfl_xor(ea, o, 64);
-      eb += __shfl_xor(eb, o, 64);
-    }
-    if (tid < 2) {
-      const float m = kMedOverRms * (sqrtf(tid == 0 ? ea : eb) * inv_w);
-      s_br[2 * tid + 0] = m * (1.0f - bracket_of<N>());
-      s_br[2 * tid + 1] = m * (1.0f + bracket_of<N>());
-      s_cnt[tid] = 0;
-    }
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int total = pbn * CB;
+  const int per = (total + 7) >> 3;  // tiles per XCD
+  const int b = blockIdx.x;
+  const int L = (b & 7) * per + (b >> 3);
+  if ((b >> 3) >= per || L >= total) return;
+  const int pl = L / CB, cb = L % CB;
+  FirstRegs<Sh, COLS, NT> x;
+  {  // rows outside the stored band read as zero through the range check
+    const auto rm = buf_rsrc(M + (size_t)pl * n_rows * N + cb * COLS, (uint32_t)n_rows * N * 8u);
+    fft_first_load<Sh, COLS, NT, false>(
+        tid,
+        [&](int f, int i) {
+          const int slot = band_slot(i, N, vmax);
+          return buf_load_f2(rm, slot >= 0 ? (uint32_t)(slot * N + f) * 8u : kNoLoad);
+        },
+        x);
   }
+  float e = 0.f;  // grid energy of image a (even threads) or b (odd threads)
+  {
+    const auto re = buf_rsrc(epart + (size_t)pl * n_rp * 2, (uint32_t)n_rp * 8u);
+    float ep[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int t = tid + q * NT;
+      ep[q] = buf_load_f1(re, t < 2 * n_rp ? (uint32_t)t * 4u : kNoLoad);
+    }
+    // keep the scheduler from starting the transform before every load is issued
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) e += ep[q];
+  }
+  fft_first_dft<Sh, COLS, NT>(x);
+#pragma unroll
+  for (int o = 2; o < 64; o <<= 1) e += __shfl_xor(e, o, 64);
+  fft_first_store<Sh, COLS, NT, S, false, true>(buf, tw, tid, x);
+  if (lane < 2) s_e[lane][wid] = e;
+  if (tid < 2) s_cnt[tid] = 0;
   __syncthreads();
+  float ea = 0.f, eb = 0.f;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    ea += s_e[0][w];
+    eb += s_e[1][w];
+  }
+  const float ma = kMedOverRms * (sqrtf(ea) * inv_w), mb = kMedOverRms * (sqrtf(eb) * inv_w);
+  const float lo_a = ma * (1.0f - bracket_of<N>()), hi_a = ma * (1.0f + bracket_of<N>());
+  const float lo_b = mb * (1.0f - bracket_of<N>()), hi_b = mb * (1.0f + bracket_of<N>());
   const bool hasb = 2 * (p0 + pl) + 1 < nimg_w;
-  const float lo_a = s_br[0], hi_a = s_br[1], lo_b = s_br[2], hi_b = s_br[3];
-  // this workgroup's list regions (capb values each) for the two images
+  const int x0 = cb * COLS;
+  // this tile's list regions (capb values each) for the two images
   float *la = list + ((size_t)(2 * pl) * CB + cb) * capb;
   float *lb = list + ((size_t)(2 * pl + 1) * CB + cb) * capb;
   float bva = -__builtin_inff(), bvb = -__builtin_inff();
   int bia = 0x7fffffff, bib = 0x7fffffff;
   uint32_t ca = 0, cbn = 0;
-  const float2 *Mp = M + (size_t)pl * n_rows * N + x0;
-  const int lane = tid & 63;
-  fft_inverse_blocks<N, COLS, NT, S, false>(
-      buf, tw, tid,
-      [&](int f, int i) {  // branch-free: every load is issued before any is used
-        const int slot = band_slot(i, N, vmax);
-        const float2 m = Mp[(size_t)max(slot, 0) * N + f];
-        return slot >= 0 ? m : make_float2(0.f, 0.f);
-      },
-      [&](int f, int k0, int ks, auto &v) {
-        constexpr int R = sizeof(v) / sizeof(v[0]);
-        uint32_t ma = 0, mb = 0;  // bracket membership, one bit per output
+  fft_rest_blocks<Sh, COLS, NT, S, false, true>(buf, tw, tid, [&](int f, int k0, int ks, auto &v) {
+    constexpr int R = sizeof(v) / sizeof(v[0]);
+    uint32_t ma_ = 0, mb_ = 0;  // bracket membership, one bit per output
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int idx = (k0 + r * ks) * N + x0 + f;
-          const float pa = v[r].x * inv_w;
-          if (pa > bva || (pa == bva && idx < bia)) {
-            bva = pa;
-            bia = idx;
-          }
-          const float aa = fabsf(pa);
-          ca += aa < lo_a;
-          ma |= (aa >= lo_a && aa < hi_a) ? (1u << r) : 0u;
-          if (hasb) {
-            const float pb = v[r].y * inv_w;
-            if (pb > bvb || (pb == bvb && idx < bib)) {
-              bvb = pb;
-              bib = idx;
-            }
-            const float ab = fabsf(pb);
-            cbn += ab < lo_b;
-            mb |= (ab >= lo_b && ab < hi_b) ? (1u << r) : 0u;
-          }
+    for (int r = 0; r < R; ++r) {
+      const int idx = (k0 + r * ks) * N + x0 + f;
+      const float pa = v[r].x * inv_w;
+      if (pa > bva || (pa == bva && idx < bia)) {
+        bva = pa;
+        bia = idx;
+      }
+      const float aa = fabsf(pa);
+      ca += aa < lo_a;
+      ma_ |= (aa >= lo_a && aa < hi_a) ? (1u << r) : 0u;
+      if (hasb) {
+        const float pb = v[r].y * inv_w;
+        if (pb > bvb || (pb == bvb && idx < bib)) {
+          bvb = pb;
+          bib = idx;
         }
-        // reserve list space once per wave, then write this thread's values
-        const uint32_t na = __popc(ma), nb = __popc(mb);
-        uint32_t pa_ = na, pb_ = nb;  // inclusive prefix sums over the wave
+        const float ab = fabsf(pb);
+        cbn += ab < lo_b;
+        mb_ |= (ab >= lo_b && ab < hi_b) ? (1u << r) : 0u;
+      }
+    }
+    // reserve list space once per wave and image (LDS counters), then write
+    // this thread's values
+    const uint32_t na = __popc(ma_), nb = __popc(mb_);
+    uint32_t pa_ = na, pb_ = nb;  // inclusive prefix sums over the wave
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const uint32_t ya = __shfl_up(pa_, o, 64), yb = __shfl_up(pb_, o, 64);
-          if (lane >= o) {
-            pa_ += ya;
-            pb_ += yb;
-          }
-        }
-        uint32_t basea = 0, baseb = 0;
-        if (lane == 63) {  // one reservation per wave and image, in LDS
-          basea = pa_ ? atomicAdd(&s_cnt[0], pa_) : 0u;
-          baseb = pb_ ? atomicAdd(&s_cnt[1], pb_) : 0u;
-        }
-        basea = __shfl(basea, 63, 64) + pa_ - na;
-        baseb = __shfl(baseb, 63, 64) + pb_ - nb;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t ya = __shfl_up(pa_, o, 64), yb = __shfl_up(pb_, o, 64);
+      if (lane >= o) {
+        pa_ += ya;
+        pb_ += yb;
+      }
+    }
+    uint32_t basea = 0, baseb = 0;
+    if (lane == 63) {
+      basea = pa_ ? atomicAdd(&s_cnt[0], pa_) : 0u;
+      baseb = pb_ ? atomicAdd(&s_cnt[1], pb_) : 0u;
+    }
+    basea = __shfl(basea, 63, 64) + pa_ - na;
+    baseb = __shfl(baseb, 63, 64) + pb_ - nb;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          if (ma & (1u << r)) {
-            if (basea < (uint32_t)capb) la[basea] = fabsf(v[r].x * inv_w);
-            ++basea;
-          }
-          if (mb & (1u << r)) {
-            if (baseb < (uint32_t)capb) lb[baseb] = fabsf(v[r].y * inv_w);
-            ++baseb;
-          }
-        }
-      });
+    for (int r = 0; r < R; ++r) {
+      if (ma_ & (1u << r)) {
+        if (basea < (uint32_t)capb) la[basea] = fabsf(v[r].x * inv_w);
+        ++basea;
+      }
+      if (mb_ & (1u << r)) {
+        if (baseb < (uint32_t)capb) lb[baseb] = fabsf(v[r].y * inv_w);
+        ++baseb;
+      }
+    }
+  });
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const float ova = __shfl_xor(bva, o, 64);
@@ -446,8 +478,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
     ca += __shfl_xor(ca, o, 64);
     cbn += __shfl_xor(cbn, o, 64);
   }
-  const int wid = tid >> 6;
-  if ((tid & 63) == 0) {
+  if (lane == 0) {
     w_v[0][wid] = bva;
     w_i[0][wid] = bia;
     w_c[0][wid] = ca;
@@ -472,8 +503,8 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
     cp.maxi = i;
     cp.cnt_lo = c;
     cp.n = s_cnt[tid];
-    cp.lo = s_br[2 * tid + 0];
-    cp.hi = s_br[2 * tid + 1];
+    cp.lo = tid == 0 ? lo_a : lo_b;
+    cp.hi = tid == 0 ? hi_a : hi_b;
     part[(size_t)(2 * pl + tid) * CB + cb] = cp;
   }
 }
@@ -941,8 +972,9 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
                p->n_rows, p->d_zs_off, p->d_zs_u, p->d_zs_ck, p->d_zs_cmk, p->d_tw, M,
                epart)));
   const float inv_w = 1.0f / (float)p->W;
+  const int cgrid = (pbn * sh.cbp + 7) / 8 * 8;
   RF_TIMED(tm, RF_K_COLS,
-           (k_cols_stats<N><<<(unsigned)(pbn * sh.cbp), ColCfg<N>::NT, 0, s>>>(
+           (k_cols_stats<N><<<(unsigned)cgrid, ColCfg<N>::NT, 0, s>>>(
                M, p->n_rows, p->vmax, nimg_w, p0, pbn, inv_w, p->d_tw, epart, p->n_rp,
                part, list, sh.capb)));
   hipStream_t ss = s;

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(RowCfg<N>::NT) void k_rows_dense(
     const float2 *__restrict__ grid, int nimg, const int32_t *__restrict__ rows, int n_rows,
     int row_blocks, const float2 *__restrict__ tw, float2 *__restrict__ M) {
   constexpr int F = RowCfg<N>::F, NT = RowCfg<N>::NT, S = RowCfg<N>::STRIDE;
-  constexpr int PS = FftPad<N>::PS;
+  constexpr int PS = RowFft<N>::PS;
   __shared__ float2 buf[F * S];
   const int pair = blockIdx.x / row_blocks;
   const int slot0 = (blockIdx.x % row_blocks) * F;
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(RowCfg<N>::NT) void k_rows_dense(
     buf[f * S + pidx<PS>(u)] = z;
   }
   __syncthreads();
-  fft_inverse<N, F, NT, S, true>(
+  fft_inverse<RowFft<N>, F, NT, S, true>(
       buf, tw, tid, [&](int f, int i) { return buf[f * S + pidx<PS>(i)]; },
       [&](int f, int x, float2 v) {
         const int slot = slot0 + f;
@@ -69,16 +69,16 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_image(
   const int pair = blockIdx.x / CB;
   const int x0 = (blockIdx.x % CB) * COLS;
   const int tid = threadIdx.x;
-  const float2 *Mp = M + (size_t)pair * n_rows * N + x0;
+  // rows outside the stored band read as zero through the range check
+  const auto rm = buf_rsrc(M + (size_t)pair * n_rows * N + x0, (uint32_t)n_rows * N * 8u);
   float *ia = img + (size_t)(2 * pair) * N * N + x0;
   float *ib = ia + (size_t)N * N;
   const bool hasb = 2 * pair + 1 < nimg;
-  fft_inverse<N, COLS, NT, S, false>(
+  fft_inverse<ColFft<N>, COLS, NT, S, false>(
       buf, tw, tid,
-      [&](int f, int i) {  // branch-free: every load is issued before any is used
+      [&](int f, int i) {
         const int slot = band_slot(i, N, vmax);
-        const float2 m = Mp[(size_t)max(slot, 0) * N + f];
-        return slot >= 0 ? m : make_float2(0.f, 0.f);
+        return buf_load_f2(rm, slot >= 0 ? (uint32_t)(slot * N + f) * 8u : kNoLoad);
       },
       [&](int f, int y, float2 v) {
         ia[(size_t)y * N + f] = v.x * inv_w;
