@@ -139,16 +139,16 @@ struct FftShape {
   static constexpr int PADDED = N + (N >> PS);
 };
 
-// Row transforms (along u): two register passes of radix up to 32 (three at
-// 2048).  Column transforms (along v): passes of radix up to 16, so that a
-// thread holds 16 values and four waves per SIMD fit in the register file.
+// Row transforms (along u) and column transforms (along v).  From 512 up the
+// passes are of radix up to 16, so that a thread of a 512-thread workgroup
+// holds 16 values and four waves per SIMD fit in the register file.
 template <int N> struct RowFft;
 template <> struct RowFft<64> : FftShape<64, 8, 8, 1> {};
 template <> struct RowFft<128> : FftShape<128, 16, 8, 1> {};
 template <> struct RowFft<256> : FftShape<256, 16, 16, 1> {};
-template <> struct RowFft<512> : FftShape<512, 32, 16, 1> {};
-template <> struct RowFft<1024> : FftShape<1024, 32, 32, 1> {};
-template <> struct RowFft<2048> : FftShape<2048, 32, 8, 8> {};
+template <> struct RowFft<512> : FftShape<512, 8, 8, 8> {};
+template <> struct RowFft<1024> : FftShape<1024, 16, 8, 8> {};
+template <> struct RowFft<2048> : FftShape<2048, 16, 16, 8> {};
 template <int N> struct ColFft;
 template <> struct ColFft<64> : FftShape<64, 8, 8, 1> {};
 template <> struct ColFft<128> : FftShape<128, 16, 8, 1> {};
