@@ -399,65 +399,104 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
   const float lo_b = mb * (1.0f - bracket_of<N>()), hi_b = mb * (1.0f + bracket_of<N>());
   const bool hasb = 2 * (p0 + pl) + 1 < nimg_w;
   const int x0 = cb * COLS;
+  // the brackets as bit patterns: [lo, hi) is u - ulo < uwid (unsigned)
+  const uint32_t ulo_a = __float_as_uint(lo_a), uwid_a = __float_as_uint(hi_a) - ulo_a;
+  const uint32_t ulo_b = __float_as_uint(lo_b), uwid_b = __float_as_uint(hi_b) - ulo_b;
   // this tile's list regions (capb values each) for the two images
-  float *la = list + ((size_t)(2 * pl) * CB + cb) * capb;
-  float *lb = list + ((size_t)(2 * pl + 1) * CB + cb) * capb;
+  const auto rla = buf_rsrc(list + ((size_t)(2 * pl) * CB + cb) * capb, (uint32_t)capb * 4u);
+  const auto rlb = buf_rsrc(list + ((size_t)(2 * pl + 1) * CB + cb) * capb, (uint32_t)capb * 4u);
   float bva = -__builtin_inff(), bvb = -__builtin_inff();
   int bia = 0x7fffffff, bib = 0x7fffffff;
   uint32_t ca = 0, cbn = 0;
   fft_rest_blocks<Sh, COLS, NT, S, false, true>(buf, tw, tid, [&](int f, int k0, int ks, auto &v) {
     constexpr int R = sizeof(v) / sizeof(v[0]);
-    uint32_t ma_ = 0, mb_ = 0;  // bracket membership, one bit per output
+    // Image b is computed even when the pair has no second image: its values
+    // are then never used (no record is written for it and no select reads
+    // its list region), and the loop stays free of branches.
+    //
+    // The R outputs come in increasing row order, so within this butterfly a
+    // strict comparison keeps the lowest flat index among equal values; the
+    // butterfly's best then merges into the running best by (value, index).
+    float ma = -__builtin_inff(), mb = -__builtin_inff();
+    int ra = 0, rb = 0;
+    float aa[R], ab[R];
+    uint64_t ba[R], bb[R];  // wave masks of bracket members, per output row
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int idx = (k0 + r * ks) * N + x0 + f;
-      const float pa = v[r].x * inv_w;
-      if (pa > bva || (pa == bva && idx < bia)) {
-        bva = pa;
-        bia = idx;
+      const float pa = v[r].x * inv_w, pb = v[r].y * inv_w;
+      if (pa > ma) {
+        ma = pa;
+        ra = r;
       }
-      const float aa = fabsf(pa);
-      ca += aa < lo_a;
-      ma_ |= (aa >= lo_a && aa < hi_a) ? (1u << r) : 0u;
-      if (hasb) {
-        const float pb = v[r].y * inv_w;
-        if (pb > bvb || (pb == bvb && idx < bib)) {
-          bvb = pb;
-          bib = idx;
+      if (pb > mb) {
+        mb = pb;
+        rb = r;
+      }
+      aa[r] = fabsf(pa);
+      ab[r] = fabsf(pb);
+      // wave-uniform count below the bracket; members by one unsigned compare
+      ca += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(aa[r] < lo_a));
+      cbn += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(ab[r] < lo_b));
+      ba[r] = __builtin_amdgcn_ballot_w64(__float_as_uint(aa[r]) - ulo_a < uwid_a);
+      bb[r] = __builtin_amdgcn_ballot_w64(__float_as_uint(ab[r]) - ulo_b < uwid_b);
+    }
+    {
+      const int ia = (k0 + ra * ks) * N + x0 + f;
+      if (better(ma, ia, bva, bia)) {
+        bva = ma;
+        bia = ia;
+      }
+      const int ib = (k0 + rb * ks) * N + x0 + f;
+      if (better(mb, ib, bvb, bib)) {
+        bvb = mb;
+        bib = ib;
+      }
+    }
+    // Compact the members into the list regions: one LDS reservation per
+    // wave and image; a member's slot is the reservation plus the members
+    // before it (earlier rows, then lower lanes).  Slots at or past capb fall
+    // outside the buffer resource and are dropped by the hardware.  Membership
+    // is tested on the bit patterns (for values >= 0 the integer order is the
+    // float order, NaN included: it lies above every bound).
+    uint32_t na = 0, nb = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      na += (uint32_t)__popcll(ba[r]);
+      nb += (uint32_t)__popcll(bb[r]);
+    }
+    if (na | nb) {
+      uint32_t base = 0;
+      if (lane == 0) {
+        const uint32_t x = na ? atomicAdd(&s_cnt[0], na) : 0u;
+        const uint32_t y = nb ? atomicAdd(&s_cnt[1], nb) : 0u;
+        base = x | (y << 16);  // both below 2^16: a tile holds COLS N <= 8192 pixels
+      }
+      base = __builtin_amdgcn_readfirstlane(base);
+      uint32_t oa = base & 0xffffu, ob = base >> 16;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (ba[r]) {
+          const uint32_t below =
+              __builtin_amdgcn_mbcnt_hi((uint32_t)(ba[r] >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)ba[r], 0u));
+          const uint32_t u = __float_as_uint(aa[r]);
+          __builtin_amdgcn_raw_buffer_store_b32(u, rla,
+                                                u - ulo_a < uwid_a ? (int)((oa + below) * 4u)
+                                                                   : (int)kNoLoad,
+                                                0, 0);
+          oa += (uint32_t)__popcll(ba[r]);
         }
-        const float ab = fabsf(pb);
-        cbn += ab < lo_b;
-        mb_ |= (ab >= lo_b && ab < hi_b) ? (1u << r) : 0u;
-      }
-    }
-    // reserve list space once per wave and image (LDS counters), then write
-    // this thread's values
-    const uint32_t na = __popc(ma_), nb = __popc(mb_);
-    uint32_t pa_ = na, pb_ = nb;  // inclusive prefix sums over the wave
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t ya = __shfl_up(pa_, o, 64), yb = __shfl_up(pb_, o, 64);
-      if (lane >= o) {
-        pa_ += ya;
-        pb_ += yb;
-      }
-    }
-    uint32_t basea = 0, baseb = 0;
-    if (lane == 63) {
-      basea = pa_ ? atomicAdd(&s_cnt[0], pa_) : 0u;
-      baseb = pb_ ? atomicAdd(&s_cnt[1], pb_) : 0u;
-    }
-    basea = __shfl(basea, 63, 64) + pa_ - na;
-    baseb = __shfl(baseb, 63, 64) + pb_ - nb;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (ma_ & (1u << r)) {
-        if (basea < (uint32_t)capb) la[basea] = fabsf(v[r].x * inv_w);
-        ++basea;
-      }
-      if (mb_ & (1u << r)) {
-        if (baseb < (uint32_t)capb) lb[baseb] = fabsf(v[r].y * inv_w);
-        ++baseb;
+        if (bb[r]) {
+          const uint32_t below =
+              __builtin_amdgcn_mbcnt_hi((uint32_t)(bb[r] >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bb[r], 0u));
+          const uint32_t u = __float_as_uint(ab[r]);
+          __builtin_amdgcn_raw_buffer_store_b32(u, rlb,
+                                                u - ulo_b < uwid_b ? (int)((ob + below) * 4u)
+                                                                   : (int)kNoLoad,
+                                                0, 0);
+          ob += (uint32_t)__popcll(bb[r]);
+        }
       }
     }
   });
@@ -475,8 +514,6 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
       bvb = ovb;
       bib = oib;
     }
-    ca += __shfl_xor(ca, o, 64);
-    cbn += __shfl_xor(cbn, o, 64);
   }
   if (lane == 0) {
     w_v[0][wid] = bva;
