@@ -32,6 +32,7 @@ namespace {
 
 using namespace rf;
 
+constexpr int kLanes = 2;              // concurrent batch pipelines (streams) of a segment search
 constexpr int kMaxW = 8;               // widths handled by one pass over the segment
 constexpr float kMedOverRms = 0.6745f; // median |x| / rms of a zero-mean Gaussian
 // half-width of the median bracket (relative): the bracket holds about 0.86%
@@ -362,8 +363,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
     fft_first_load<Sh, COLS, NT, false>(
         tid,
         [&](int f, int i) {
-          const int slot = band_slot(i, N, vmax);
-          return buf_load_f2(rm, slot >= 0 ? (uint32_t)(slot * N + f) * 8u : kNoLoad);
+          return buf_load_f2(rm, (uint32_t)(band_slot_raw(i, N, vmax) * N + f) * 8u);
         },
         x);
   }
@@ -853,9 +853,10 @@ Shape shape_n(const rf_plan *p) {
   s.capb = ColCfg<N>::COLS * N / 16;
   static_assert(N / ColCfg<N>::COLS <= kMaxCB, "column workgroups per image");
   static_assert(ColCfg<N>::COLS * N / 16 >= 128, "a list region holds the staged 128 values");
-  // pairs per batch: keep the row-transformed batch (~128 MB) cache-resident
+  // pairs per batch: the row-transformed batches of all lanes (~240 MB)
+  // stay resident in the last-level cache between the row and column passes
   const size_t per_pair = (size_t)std::max(1, p->n_rows) * N * sizeof(float2);
-  const int pb = (int)std::max<size_t>(s.pbw, ((size_t)128 << 20) / per_pair);
+  const int pb = (int)std::max<size_t>(s.pbw, ((size_t)240 << 20) / kLanes / per_pair);
   s.pb = std::min(64, (pb / s.pbw) * s.pbw);
   return s;
 }
@@ -871,10 +872,16 @@ Shape shape_of(const rf_plan *p) {
   }
 }
 
-// Per-batch records are double-buffered: the select of batch b runs on a side
-// stream while batch b+1 is transformed.
+// Buffers of one lane (a stream that runs whole batches: cell sums, rows,
+// columns and select, in order).
+struct LaneBufs {
+  size_t cv, m, epart, part, list;
+};
+// The dedispersed, resampled samples are double-buffered by DM parity, so
+// that the next DM's pass over the segment overlaps this DM's batches.
 struct Layout {
-  size_t vi, cv, m, epart[2], part[2], list[2], fb, dd, rs, grid, img, mws, total;
+  size_t vi[2], fb, dd, rs, grid, img, mws, total;
+  LaneBufs lane[kLanes];
   std::vector<size_t> vi_off;  // per width, in float2 units
 };
 
@@ -893,13 +900,14 @@ Layout layout_of(const rf_plan *p) {
     o += align_up(bytes);
     return at;
   };
-  L.vi = take(vi_elems * sizeof(float2));
-  L.cv = take((size_t)2 * sh.pb * std::max(1, p->n_cells) * sizeof(float2));
-  L.m = take((size_t)sh.pb * p->n_rows * p->npix * sizeof(float2));
-  for (int d = 0; d < 2; ++d) {
-    L.epart[d] = take((size_t)sh.pb * std::max(1, p->n_rp) * 2 * sizeof(float));
-    L.part[d] = take((size_t)2 * sh.pb * sh.cbp * sizeof(ColPart));
-    L.list[d] = take((size_t)2 * sh.pb * sh.cbp * sh.capb * sizeof(float));
+  for (int d = 0; d < 2; ++d) L.vi[d] = take(vi_elems * sizeof(float2));
+  for (int k = 0; k < kLanes; ++k) {
+    LaneBufs &b = L.lane[k];
+    b.cv = take((size_t)2 * sh.pb * std::max(1, p->n_cells) * sizeof(float2));
+    b.m = take((size_t)sh.pb * p->n_rows * p->npix * sizeof(float2));
+    b.epart = take((size_t)sh.pb * std::max(1, p->n_rp) * 2 * sizeof(float));
+    b.part = take((size_t)2 * sh.pb * sh.cbp * sizeof(ColPart));
+    b.list = take((size_t)2 * sh.pb * sh.cbp * sh.capb * sizeof(float));
   }
   L.fb = take(((size_t)p->n_images + 1) * sizeof(int32_t));
   // buffers of the exact fallback (step chain on one image pair)
@@ -960,42 +968,56 @@ struct Timer {
     RF_HIP_TRY((tm)->mark(-1));          \
   } while (0)
 
-// Side stream and events that overlap each batch's select with the next
-// batch's transforms.  Created per call; default priority.
-struct Overlap {
-  hipStream_t side = nullptr;
-  hipEvent_t cols_done[2] = {nullptr, nullptr}, sel_done[2] = {nullptr, nullptr};
-  bool used[2] = {false, false};
+// Streams and events of a segment search: kLanes lane streams, a stream for
+// the per-DM pass over the segment, and the events ordering them.  Created
+// per call, default priority.
+struct Lanes {
+  hipStream_t lane[kLanes] = {}, drs = nullptr;
+  hipEvent_t start = nullptr, drs_done[2] = {}, lane_dm[kLanes][2] = {}, lane_end[kLanes] = {};
   hipError_t init() {
-    hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
-    for (int d = 0; d < 2 && e == hipSuccess; ++d) {
-      e = hipEventCreateWithFlags(&cols_done[d], hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&sel_done[d], hipEventDisableTiming);
+    hipError_t e = hipStreamCreateWithFlags(&drs, hipStreamNonBlocking);
+    for (int k = 0; k < kLanes && e == hipSuccess; ++k)
+      e = hipStreamCreateWithFlags(&lane[k], hipStreamNonBlocking);
+    auto ev = [&](hipEvent_t &x) {
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+    };
+    ev(start);
+    for (int d = 0; d < 2; ++d) ev(drs_done[d]);
+    for (int k = 0; k < kLanes; ++k) {
+      ev(lane_dm[k][0]);
+      ev(lane_dm[k][1]);
+      ev(lane_end[k]);
     }
     return e;
   }
-  ~Overlap() {
-    for (int d = 0; d < 2; ++d) {
-      if (cols_done[d]) (void)hipEventDestroy(cols_done[d]);
-      if (sel_done[d]) (void)hipEventDestroy(sel_done[d]);
+  ~Lanes() {
+    auto de = [](hipEvent_t x) {
+      if (x) (void)hipEventDestroy(x);
+    };
+    de(start);
+    for (int d = 0; d < 2; ++d) de(drs_done[d]);
+    for (int k = 0; k < kLanes; ++k) {
+      de(lane_dm[k][0]);
+      de(lane_dm[k][1]);
+      de(lane_end[k]);
+      if (lane[k]) (void)hipStreamDestroy(lane[k]);
     }
-    if (side) (void)hipStreamDestroy(side);
+    if (drs) (void)hipStreamDestroy(drs);
   }
 };
 
+// One batch (pbn image pairs from p0 of one (DM, width)), every launch on
+// stream s with the lane's buffers.
 template <int N>
 rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_w, int p0,
                   int pbn, int dm_idx, int width_idx, int width, int64_t stat_base, char *ws,
-                  const Layout &L, int db, rf_image_stats *stats, rf_candidate *cand, int cap,
-                  int32_t *ncand, hipStream_t s, Timer *tm, Overlap *ov) {
-  float2 *M = (float2 *)(ws + L.m);
-  float2 *cv = (float2 *)(ws + L.cv);
-  float *epart = (float *)(ws + L.epart[db]);
-  ColPart *part = (ColPart *)(ws + L.part[db]);
-  float *list = (float *)(ws + L.list[db]);
-  int32_t *fb = (int32_t *)(ws + L.fb);
-  // the select that last used this buffer set must be done with it
-  if (ov && ov->used[db]) RF_HIP_TRY(hipStreamWaitEvent(s, ov->sel_done[db], 0));
+                  const LaneBufs &B, int32_t *fb, rf_image_stats *stats, rf_candidate *cand,
+                  int cap, int32_t *ncand, hipStream_t s, Timer *tm) {
+  float2 *M = (float2 *)(ws + B.m);
+  float2 *cv = (float2 *)(ws + B.cv);
+  float *epart = (float *)(ws + B.epart);
+  ColPart *part = (ColPart *)(ws + B.part);
+  float *list = (float *)(ws + B.list);
   const int npb = (pbn + sh.pbw - 1) / sh.pbw;
   const int nimg_b = std::min(2 * pbn, nimg_w - 2 * p0);  // images in this batch
   const int groups = (nimg_b + 8 * kCellImgs - 1) / (8 * kCellImgs);
@@ -1014,31 +1036,21 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
            (k_cols_stats<N><<<(unsigned)cgrid, ColCfg<N>::NT, 0, s>>>(
                M, p->n_rows, p->vmax, nimg_w, p0, pbn, inv_w, p->d_tw, epart, p->n_rp,
                part, list, sh.capb)));
-  hipStream_t ss = s;
-  if (ov) {
-    RF_HIP_TRY(hipEventRecord(ov->cols_done[db], s));
-    RF_HIP_TRY(hipStreamWaitEvent(ov->side, ov->cols_done[db], 0));
-    ss = ov->side;
-  }
   RF_TIMED(tm, RF_K_SELECT,
-           (k_select<<<(unsigned)(2 * pbn), kSelThreads, 0, ss>>>(
+           (k_select<<<(unsigned)(2 * pbn), kSelThreads, 0, s>>>(
                part, list, sh.cbp, sh.capb, nimg_w, p0, pbn, N, dm_idx, width_idx, width,
                stat_base, stats, cand, cap, ncand, fb, fb + 1, p->threshold, p->t_begin,
                p->t_end)));
-  if (ov) {
-    RF_HIP_TRY(hipEventRecord(ov->sel_done[db], ov->side));
-    ov->used[db] = true;
-  }
   return RF_OK;
 }
 
 rf_status batch(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_w, int p0, int pbn,
                 int dm_idx, int width_idx, int width, int64_t stat_base, char *ws,
-                const Layout &L, int db, rf_image_stats *stats, rf_candidate *cand, int cap,
-                int32_t *ncand, hipStream_t s, Timer *tm, Overlap *ov) {
+                const LaneBufs &B, int32_t *fb, rf_image_stats *stats, rf_candidate *cand,
+                int cap, int32_t *ncand, hipStream_t s, Timer *tm) {
 #define RF_BATCH(NN)                                                                            \
-  return batch_n<NN>(p, sh, vi, nimg_w, p0, pbn, dm_idx, width_idx, width, stat_base, ws, L, \
-                     db, stats, cand, cap, ncand, s, tm, ov)
+  return batch_n<NN>(p, sh, vi, nimg_w, p0, pbn, dm_idx, width_idx, width, stat_base, ws, B, \
+                     fb, stats, cand, cap, ncand, s, tm)
   switch (p->npix) {
     case 64: RF_BATCH(64);
     case 128: RF_BATCH(128);
@@ -1132,20 +1144,40 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
     // produces the (zero) statistics
     return run_segment_steps(p, vis, cand, cap, ncand, stats, ws, ws_bytes, s);
   }
-  Overlap overlap;
-  Overlap *ov = nullptr;
+  // Untimed: kLanes lane streams take the batches round robin and a stream of
+  // its own runs each DM's pass over the segment into the sample buffer of
+  // that DM's parity.  The pass of DM i waits until every lane has finished
+  // the batches of DM i - 2 (the last readers of that buffer); a lane's
+  // batches of DM i wait for the pass of DM i.  Timed: everything in order on
+  // the caller's stream, so that kernel durations do not overlap.
+  Lanes lanes;
+  const int nl = kt ? 1 : kLanes;
+  hipStream_t ls[kLanes], ds = s;
+  for (int k = 0; k < kLanes; ++k) ls[k] = s;
   if (!kt) {
-    RF_HIP_TRY(overlap.init());
-    ov = &overlap;
+    RF_HIP_TRY(lanes.init());
+    RF_HIP_TRY(hipEventRecord(lanes.start, s));
+    RF_HIP_TRY(hipStreamWaitEvent(lanes.drs, lanes.start, 0));
+    ds = lanes.drs;
+    for (int k = 0; k < kLanes; ++k) {
+      ls[k] = lanes.lane[k];
+      RF_HIP_TRY(hipStreamWaitEvent(ls[k], lanes.start, 0));
+    }
   }
   int nbatch = 0;
-  float2 *vi = (float2 *)(ws + L.vi);
   std::vector<float2 *> vi_out(p->nwidth);
-  for (int j = 0; j < p->nwidth; ++j) vi_out[j] = vi + L.vi_off[j];
   for (int i = 0; i < p->ndm; ++i) {
+    float2 *vi = (float2 *)(ws + L.vi[i & 1]);
+    for (int j = 0; j < p->nwidth; ++j) vi_out[j] = vi + L.vi_off[j];
+    if (!kt && i >= 2)
+      for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipStreamWaitEvent(ds, lanes.lane_dm[k][i & 1], 0));
     st = drs_timed(p, p->d_delay + (size_t)i * p->nchan, vis, p->width.data(), p->nwidth,
-                   vi_out.data(), s, tm);
+                   vi_out.data(), ds, tm);
     if (st != RF_OK) return st;
+    if (!kt) {
+      RF_HIP_TRY(hipEventRecord(lanes.drs_done[i & 1], ds));
+      for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipStreamWaitEvent(ls[k], lanes.drs_done[i & 1], 0));
+    }
     for (int j = 0; j < p->nwidth; ++j) {
       const int w = p->width[j];
       const int nimg_w = p->nint / w;
@@ -1153,17 +1185,22 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
       const int64_t base = p->img_base[(size_t)i * p->nwidth + j];
       for (int p0 = 0; p0 < npairs; p0 += sh.pb) {
         const int pbn = std::min(sh.pb, npairs - p0);
-        st = batch(p, sh, vi_out[j], nimg_w, p0, pbn, i, j, w, base, ws, L, nbatch & 1, stats,
-                   cand, cap, ncand, s, tm, ov);
+        const int k = nbatch % nl;
+        st = batch(p, sh, vi_out[j], nimg_w, p0, pbn, i, j, w, base, ws, L.lane[k], fb, stats,
+                   cand, cap, ncand, ls[k], tm);
         if (st != RF_OK) return st;
         ++nbatch;
       }
     }
+    if (!kt)
+      for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipEventRecord(lanes.lane_dm[k][i & 1], ls[k]));
     RF_HIP_TRY(tm->flush());
   }
-  if (ov) {  // join: the caller's stream waits for the last selects
-    for (int d = 0; d < 2; ++d)
-      if (ov->used[d]) RF_HIP_TRY(hipStreamWaitEvent(s, ov->sel_done[d], 0));
+  if (!kt) {  // join: the caller's stream waits for every lane
+    for (int k = 0; k < nl; ++k) {
+      RF_HIP_TRY(hipEventRecord(lanes.lane_end[k], ls[k]));
+      RF_HIP_TRY(hipStreamWaitEvent(s, lanes.lane_end[k], 0));
+    }
   }
   // exact fallback for the images whose median left the bracket
   int32_t nfb = 0;

@@ -76,10 +76,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_image(
   const bool hasb = 2 * pair + 1 < nimg;
   fft_inverse<ColFft<N>, COLS, NT, S, false>(
       buf, tw, tid,
-      [&](int f, int i) {
-        const int slot = band_slot(i, N, vmax);
-        return buf_load_f2(rm, slot >= 0 ? (uint32_t)(slot * N + f) * 8u : kNoLoad);
-      },
+      [&](int f, int i) { return buf_load_f2(rm, (uint32_t)(band_slot_raw(i, N, vmax) * N + f) * 8u); },
       [&](int f, int y, float2 v) {
         ia[(size_t)y * N + f] = v.x * inv_w;
         if (hasb) ib[(size_t)y * N + f] = v.y * inv_w;

@@ -216,20 +216,19 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
   }
   off.push_back((int32_t)kv.size());
   p->n_cells = (int32_t)ucell.size();
-  // Stored rows: the band |v| <= vmax of the Hermitian-symmetrised grid,
-  // v = 0..vmax then v = N-vmax..N-1, so that a row's slot is a closed form
-  // (row r -> r, or r - (N - 2 vmax - 1)); empty rows inside the band are
-  // transformed as zeros.
+  // Stored rows: the band |v| <= vmax of the Hermitian-symmetrised grid in
+  // row order v = -vmax .. vmax, so that a row's slot is (r + vmax) mod N;
+  // empty rows inside the band are transformed as zeros.
   int vmax = -1;
   for (int r = 0; r < N; ++r)
     if (occ[r]) vmax = std::max(vmax, std::min(r, N - r));
   p->vmax = vmax;
   std::vector<int32_t> rows, row_slot(N, -1);
-  for (int r = 0; r < N; ++r)
-    if (std::min(r, N - r) <= vmax) {
-      row_slot[r] = (int32_t)rows.size();
-      rows.push_back(r);
-    }
+  for (int v = -vmax; v <= vmax; ++v) {
+    const int r = v & (N - 1);
+    row_slot[r] = (int32_t)rows.size();  // = band_slot(r, N, vmax)
+    rows.push_back(r);
+  }
   p->n_rows = (int32_t)rows.size();
   std::vector<float2> tw(N);
   for (int m = 0; m < N; ++m) tw[m] = unit_root(m, N);

@@ -36,8 +36,8 @@ struct rf_plan {
   int32_t *d_contrib;       // [W] pair index b*nchan + c, sorted by (cell, pair)
   int32_t *d_ucell;         // [n_cells] linear cell (iv mod N) * N + (iu mod N), ascending
   int32_t *d_ucell_off;     // [n_cells + 1] CSR offsets into d_contrib
-  int32_t *d_rows;          // [n_rows] occupied rows, ascending
-  int32_t *d_row_slot;      // [N] compact slot of a row in d_rows, or -1 (= band_slot)
+  int32_t *d_rows;          // [n_rows] band rows in slot order: -vmax .. vmax (mod N)
+  int32_t *d_row_slot;      // [N] slot of a row in d_rows, or -1 (= band_slot)
   float2 *d_tw;             // [N] exp(+2 pi i m / N)
   // Z positions of the paired Hermitian transform, grouped by row pair
   // {v, -v} (v in [0, N/2], occupied): row pair rp has rows v = rp_row[rp]
@@ -63,9 +63,14 @@ struct rf_plan {
   std::vector<int32_t> h_cells;
 };
 
-// Slot of grid row r in the stored band |v| <= vmax, or -1 outside it.
+// Slot of grid row r in the stored band |v| <= vmax, or -1 outside it.  The
+// band is stored in row order -vmax .. vmax, so the slot is (r + vmax) mod N
+// and slots past 2 vmax are the rows outside the band: a column load at slot
+// (r + vmax) mod N falls past the end of the band exactly when r is outside.
+__host__ __device__ inline int band_slot_raw(int r, int N, int vmax) { return (r + vmax) & (N - 1); }
 __host__ __device__ inline int band_slot(int r, int N, int vmax) {
-  return r <= vmax ? r : (r >= N - vmax ? r - (N - 2 * vmax - 1) : -1);
+  const int s = band_slot_raw(r, N, vmax);
+  return s <= 2 * vmax ? s : -1;
 }
 
 #define RF_HIP_TRY(expr)                      \
