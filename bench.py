@@ -27,6 +27,28 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 FP32_PEAK_TFLOPS = 157.3    # MI355X fp32 vector, published
 
+# HBM bytes per launch of the column kernel (k_cols_stats, 1024^2 images, 16
+# image pairs per launch), from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch) of `bench.py --dms 2 --profile-only`, each
+# scaled by what the counter reads for a 1 GiB device copy (FETCH_SIZE reads
+# 524,300 KiB for 1 GiB read: x2; WRITE_SIZE 1,049,000 KiB for 1 GiB written:
+# x1).  Valid only for the kernel source with this digest (column kernel
+# section of k_fused.hip, fft.h, rf_internal.h); null once it changes.
+COLS_TRAFFIC = {"digest": "44fe95d994509fe3", "fetch_kib": 56810.0, "write_kib": 1276.0,
+                "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def cols_kernel_digest():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1802_03084_amd", "csrc")
+    k = open(os.path.join(csrc, "k_fused.hip")).read()
+    a = k.index("// ------------------------------------------------------------------ columns")
+    b = k.index("// ------------------------------------------------------------------ select")
+    h = hashlib.sha256(k[a:b].encode())
+    for f in ("fft.h", "rf_internal.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -169,9 +191,10 @@ def main():
         f"rows={plan.info['n_rows']}, workspace {ws.numel() / 1e9:.2f} GB")
 
     cap = 65536
-    if args.profile_only:
+    if args.profile_only:  # every launch in order on one stream: durations do not overlap
         times, _, n = plan.profile_segment(dvis, cap=cap, ws=ws)
-        log("profile pass: " + ", ".join(f"{k}={v[0]:.1f} ms/{v[1]}" for k, v in times.items() if v[1]))
+        log("serial profile pass: " + ", ".join(f"{k}={v[0]:.1f} ms/{v[1]} ({1e3 * v[0] / v[1]:.2f} us)"
+                                                 for k, v in times.items() if v[1]))
         return
     for w in range(args.warmup):
         t = time.perf_counter()
@@ -193,9 +216,12 @@ def main():
     log(f"{img_s:.0f} images/s, {step_s * 1e3:.1f} ms/step, RTF {seg_s / step_s:.2f}, "
         f"pulses recovered {found}/{len(p.pulses)}, candidates {n}")
 
-    # event-timed kernels of the fused path (one extra pass, not in the timed region)
+    # Event-timed kernels: one more step in the timed configuration (the same
+    # lane streams), with an event pair on each launch's own stream.  Kernels
+    # of the two lanes run concurrently, so a kernel's duration includes the
+    # time it shares the device; the serial figures are from --profile-only.
     N = p.npix
-    times, _, _ = plan.profile_segment(dvis, cap=cap, ws=ws)
+    times, _, _ = plan.profile_segment(dvis, cap=cap, ws=ws, concurrent=True)
     nw = len(p.widths)
     n_rows = plan.info["n_rows"]
     pairs = len(p.dms) * sum((p.nint // w + 1) // 2 for w in p.widths)
@@ -211,7 +237,7 @@ def main():
     kernels = {k: {"ms_total": round(v[0], 2), "launches": v[1],
                    "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None}
                for k, v in times.items() if v[1]}
-    log("fused kernels (event-timed, one pass): " +
+    log("fused kernels (event-timed step, lanes concurrent): " +
         ", ".join(f"{k}={v['ms_total']:.1f} ms/{v['launches']}" for k, v in kernels.items()))
     dom = max((k for k in algo if k in kernels), key=lambda k: kernels[k]["ms_total"])
     total_units, unit = algo[dom]
@@ -228,11 +254,26 @@ def main():
                 "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None}
     roof.update({"avg_launch_us": round(avg_s * 1e6, 2), "alg_per_launch": per_launch,
                  "launches": launches})
+    if dom == "cols" and N == 1024 and cols_kernel_digest() == COLS_TRAFFIC["digest"]:
+        t = COLS_TRAFFIC
+        roof["traffic"] = round(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
+        roof["traffic_unit"] = "B per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)"
     for k in algo:
         if k in kernels:
             u, un = algo[k]
             rate = u / (kernels[k]["ms_total"] * 1e-3)
             kernels[k]["achieved"] = (f"{rate / 1e9:.0f} GB/s" if un == "B" else f"{rate / 1e12:.2f} TFLOP/s")
+
+    # The same kernels with every launch in order on one stream (durations do
+    # not overlap): each kernel's standalone rate.
+    times_s, _, _ = plan.profile_segment(dvis, cap=cap, ws=ws, concurrent=False)
+    serial = {k: round(1e3 * v[0] / v[1], 2) for k, v in times_s.items() if v[1]}
+    log("fused kernels (event-timed, serial): " + ", ".join(f"{k}={v:.2f} us" for k, v in serial.items()))
+    if dom in serial:
+        s_avg = serial[dom] * 1e-6
+        ach_s = per_launch / s_avg / (1e9 if unit == "B" else 1e12)
+        roof["serial"] = {"avg_launch_us": serial[dom], "achieved": round(ach_s, 2),
+                          "frac": round(ach_s / roof["peak"], 4)}
 
     plain = None
     if not args.no_plain:
@@ -273,6 +314,7 @@ def main():
         "pulses_recovered": f"{found}/{len(p.pulses)}",
         "candidates": n,
         "kernels": kernels,
+        "kernels_serial_avg_us": serial,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

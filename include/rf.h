@@ -236,20 +236,28 @@ rf_status rf_search_segment(const rf_plan *plan, const void *d_vis, rf_candidate
                             void *d_ws, size_t ws_bytes, void *stream);
 
 /* Device time of the fused path's kernels, per kernel kind, measured with
- * HIP events on the launch stream (rf_search_segment_profile). */
+ * HIP events on the stream each kernel is launched on
+ * (rf_search_segment_profile). */
 enum { RF_K_DRS = 0, RF_K_ROWS = 1, RF_K_COLS = 2, RF_K_SELECT = 3, RF_K_FALLBACK = 4,
        RF_K_GRID = 5, RF_NK = 8 };
 typedef struct rf_kernel_times {
-  double ms[RF_NK];        /* summed event-timed duration, milliseconds */
-  int64_t launches[RF_NK]; /* number of launches timed                 */
+  int32_t concurrent;      /* in: 0 = every launch in order on `stream`, so that
+                              durations do not overlap; 1 = the streams and order
+                              of rf_search_segment (concurrent batches: one
+                              kernel's duration includes the time it shares the
+                              device with the other streams' kernels)          */
+  int32_t reserved;        /* in: 0                                             */
+  double ms[RF_NK];        /* out: summed event-timed duration, milliseconds   */
+  int64_t launches[RF_NK]; /* out: number of launches timed                    */
 } rf_kernel_times;
 
 /*
  * rf_search_segment_profile: rf_search_segment with an event pair recorded
- * around every kernel launch; *times receives the summed durations per
- * kernel kind.  Results are identical to rf_search_segment; the extra events
- * and one synchronisation per DM trial make it slower, so time throughput
- * with rf_search_segment.
+ * around every kernel launch; ms and launches of *times receive the summed
+ * durations per kernel kind (concurrent and reserved are read, then kept).
+ * Results are identical to rf_search_segment; the extra events and a
+ * synchronisation every few thousand launches make it slower, so time
+ * throughput with rf_search_segment.  RF_EINVAL if concurrent is not 0 or 1.
  */
 rf_status rf_search_segment_profile(const rf_plan *plan, const void *d_vis, rf_candidate *d_cand,
                                     int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,

@@ -66,7 +66,8 @@ class Candidate(ctypes.Structure):
 
 
 class KernelTimes(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", c_i64 * 8)]
+    _fields_ = [("concurrent", c_i32), ("reserved", c_i32), ("ms", ctypes.c_double * 8),
+                ("launches", c_i64 * 8)]
 
 
 KERNEL_KINDS = ["drs", "rows", "cols", "select", "fallback", "grid"]

@@ -921,15 +921,16 @@ Layout layout_of(const rf_plan *p) {
   return L;
 }
 
-// Optional event timing of every launch (rf_search_segment_profile).  When
-// timing, everything runs on the caller's stream so durations do not overlap.
+// Optional event timing of every launch (rf_search_segment_profile): an
+// event pair on the launch's own stream around each launch.  flush() waits for
+// the recorded events (on every stream given to sync()) and sums the pairs.
 struct Timer {
   rf_kernel_times *kt = nullptr;
-  hipStream_t s = nullptr;
+  std::vector<hipStream_t> streams;  // every stream that records events
   std::vector<hipEvent_t> pool;
   std::vector<int> kind;
   size_t used = 0;
-  hipError_t mark(int k) {  // call before (k >= 0) and after (k = -1) a launch
+  hipError_t mark(int k, hipStream_t s) {  // before (k >= 0) and after (k = -1) a launch
     if (!kt) return hipSuccess;
     if (used == pool.size()) {
       hipEvent_t e;
@@ -940,13 +941,16 @@ struct Timer {
     if (k >= 0) kind.push_back(k);
     return hipEventRecord(pool[used++], s);
   }
+  bool full() const { return used >= 8192; }
   hipError_t flush() {
     if (!kt || used == 0) return hipSuccess;
-    hipError_t err = hipStreamSynchronize(s);
-    if (err != hipSuccess) return err;
+    for (hipStream_t s : streams) {
+      const hipError_t err = hipStreamSynchronize(s);
+      if (err != hipSuccess) return err;
+    }
     for (size_t q = 0; q + 1 < used; q += 2) {
       float ms = 0.f;
-      err = hipEventElapsedTime(&ms, pool[q], pool[q + 1]);
+      const hipError_t err = hipEventElapsedTime(&ms, pool[q], pool[q + 1]);
       if (err != hipSuccess) return err;
       kt->ms[kind[q / 2]] += ms;
       kt->launches[kind[q / 2]] += 1;
@@ -959,13 +963,12 @@ struct Timer {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
 };
-
-#define RF_TIMED(tm, k, launch)          \
+#define RF_TIMED(tm, k, s, launch)       \
   do {                                   \
-    RF_HIP_TRY((tm)->mark(k));           \
+    RF_HIP_TRY((tm)->mark(k, s));        \
     launch;                              \
     RF_HIP_TRY(hipGetLastError());       \
-    RF_HIP_TRY((tm)->mark(-1));          \
+    RF_HIP_TRY((tm)->mark(-1, s));       \
   } while (0)
 
 // Streams and events of a segment search: kLanes lane streams, a stream for
@@ -1021,22 +1024,22 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
   const int npb = (pbn + sh.pbw - 1) / sh.pbw;
   const int nimg_b = std::min(2 * pbn, nimg_w - 2 * p0);  // images in this batch
   const int groups = (nimg_b + 8 * kCellImgs - 1) / (8 * kCellImgs);
-  RF_TIMED(tm, RF_K_GRID,
+  RF_TIMED(tm, RF_K_GRID, s,
            (k_cellsum<<<(unsigned)(groups * 8 * p->n_cblk), kCellThreads, 0, s>>>(
                vi, p->nbl * p->nchan, 2 * p0, nimg_b, p->n_cells, p->n_cblk, p->d_cblk,
                p->d_ucell_off, p->d_contrib, cv)));
-  RF_TIMED(tm, RF_K_ROWS,
+  RF_TIMED(tm, RF_K_ROWS, s,
            (k_rows_pairs<N><<<(unsigned)(npb * p->n_rp), RowPairCfg<N>::NT, 0, s>>>(
                cv, p->n_cells, nimg_w, p0, pbn, p->d_rp_row, p->d_rp_sa, p->d_rp_sb, p->n_rp,
                p->n_rows, p->d_zs_off, p->d_zs_u, p->d_zs_ck, p->d_zs_cmk, p->d_tw, M,
                epart)));
   const float inv_w = 1.0f / (float)p->W;
   const int cgrid = (pbn * sh.cbp + 7) / 8 * 8;
-  RF_TIMED(tm, RF_K_COLS,
+  RF_TIMED(tm, RF_K_COLS, s,
            (k_cols_stats<N><<<(unsigned)cgrid, ColCfg<N>::NT, 0, s>>>(
                M, p->n_rows, p->vmax, nimg_w, p0, pbn, inv_w, p->d_tw, epart, p->n_rp,
                part, list, sh.capb)));
-  RF_TIMED(tm, RF_K_SELECT,
+  RF_TIMED(tm, RF_K_SELECT, s,
            (k_select<<<(unsigned)(2 * pbn), kSelThreads, 0, s>>>(
                part, list, sh.cbp, sh.capb, nimg_w, p0, pbn, N, dm_idx, width_idx, width,
                stat_base, stats, cand, cap, ncand, fb, fb + 1, p->threshold, p->t_begin,
@@ -1088,7 +1091,7 @@ rf_status drs_timed(const rf_plan *p, const int32_t *d_delay_row, const void *vi
     ws.nw = n;
     const int tchunk = L * std::max(1, 64 / L);
     dim3 grid((nbc + kDrsThreads - 1) / kDrsThreads, (p->nint + tchunk - 1) / tchunk);
-    RF_HIP_TRY(tm->mark(RF_K_DRS));
+    RF_HIP_TRY(tm->mark(RF_K_DRS, s));
     if (p->vis_dtype == RF_CF32) {
       if (p->npol == 2)
         k_drs<float2, 2><<<grid, kDrsThreads, 0, s>>>((const float2 *)vis, d_delay_row, p->nint,
@@ -1105,7 +1108,7 @@ rf_status drs_timed(const rf_plan *p, const int32_t *d_delay_row, const void *vi
                                                        p->nint, nbc, p->nchan, tchunk, ws);
     }
     RF_HIP_TRY(hipGetLastError());
-    RF_HIP_TRY(tm->mark(-1));
+    RF_HIP_TRY(tm->mark(-1, s));
     j += n;
   }
   return RF_OK;
@@ -1128,7 +1131,7 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
                       hipStream_t s, rf_kernel_times *kt) {
   Timer timer;
   timer.kt = kt;
-  timer.s = s;
+  timer.streams.push_back(s);
   Timer *tm = &timer;
   char *ws = static_cast<char *>(ws_v);
   const Layout L = layout_of(p);
@@ -1144,17 +1147,18 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
     // produces the (zero) statistics
     return run_segment_steps(p, vis, cand, cap, ncand, stats, ws, ws_bytes, s);
   }
-  // Untimed: kLanes lane streams take the batches round robin and a stream of
-  // its own runs each DM's pass over the segment into the sample buffer of
-  // that DM's parity.  The pass of DM i waits until every lane has finished
-  // the batches of DM i - 2 (the last readers of that buffer); a lane's
-  // batches of DM i wait for the pass of DM i.  Timed: everything in order on
-  // the caller's stream, so that kernel durations do not overlap.
+  // kLanes lane streams take the batches round robin and a stream of its own
+  // runs each DM's pass over the segment into the sample buffer of that DM's
+  // parity.  The pass of DM i waits until every lane has finished the batches
+  // of DM i - 2 (the last readers of that buffer); a lane's batches of DM i
+  // wait for the pass of DM i.  Timed serially: everything in order on the
+  // caller's stream, so that kernel durations do not overlap.
+  const bool serial = kt && !kt->concurrent;
   Lanes lanes;
-  const int nl = kt ? 1 : kLanes;
+  const int nl = serial ? 1 : kLanes;
   hipStream_t ls[kLanes], ds = s;
   for (int k = 0; k < kLanes; ++k) ls[k] = s;
-  if (!kt) {
+  if (!serial) {
     RF_HIP_TRY(lanes.init());
     RF_HIP_TRY(hipEventRecord(lanes.start, s));
     RF_HIP_TRY(hipStreamWaitEvent(lanes.drs, lanes.start, 0));
@@ -1163,18 +1167,21 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
       ls[k] = lanes.lane[k];
       RF_HIP_TRY(hipStreamWaitEvent(ls[k], lanes.start, 0));
     }
+    // the caller's stream stays in the list: the exact fallback records there
+    timer.streams.insert(timer.streams.end(), ls, ls + kLanes);
+    timer.streams.push_back(ds);
   }
   int nbatch = 0;
   std::vector<float2 *> vi_out(p->nwidth);
   for (int i = 0; i < p->ndm; ++i) {
     float2 *vi = (float2 *)(ws + L.vi[i & 1]);
     for (int j = 0; j < p->nwidth; ++j) vi_out[j] = vi + L.vi_off[j];
-    if (!kt && i >= 2)
+    if (!serial && i >= 2)
       for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipStreamWaitEvent(ds, lanes.lane_dm[k][i & 1], 0));
     st = drs_timed(p, p->d_delay + (size_t)i * p->nchan, vis, p->width.data(), p->nwidth,
                    vi_out.data(), ds, tm);
     if (st != RF_OK) return st;
-    if (!kt) {
+    if (!serial) {
       RF_HIP_TRY(hipEventRecord(lanes.drs_done[i & 1], ds));
       for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipStreamWaitEvent(ls[k], lanes.drs_done[i & 1], 0));
     }
@@ -1192,16 +1199,19 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
         ++nbatch;
       }
     }
-    if (!kt)
+    if (!serial)
       for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipEventRecord(lanes.lane_dm[k][i & 1], ls[k]));
-    RF_HIP_TRY(tm->flush());
+    // timed serially: flush every DM; timed concurrently: only when the event
+    // pool is large (a flush drains the lanes)
+    if (serial || tm->full()) RF_HIP_TRY(tm->flush());
   }
-  if (!kt) {  // join: the caller's stream waits for every lane
+  if (!serial) {  // join: the caller's stream waits for every lane
     for (int k = 0; k < nl; ++k) {
       RF_HIP_TRY(hipEventRecord(lanes.lane_end[k], ls[k]));
       RF_HIP_TRY(hipStreamWaitEvent(s, lanes.lane_end[k], 0));
     }
   }
+  RF_HIP_TRY(tm->flush());
   // exact fallback for the images whose median left the bracket
   int32_t nfb = 0;
   RF_HIP_TRY(hipMemcpyAsync(&nfb, fb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1238,7 +1248,7 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
       if (st != RF_OK) return st;
       cur_j = j;
     }
-    RF_HIP_TRY(tm->mark(RF_K_FALLBACK));
+    RF_HIP_TRY(tm->mark(RF_K_FALLBACK, s));
     // image the pair the fused path used (2m, 2m+1): two real images share a
     // complex transform, so the partner is needed for identical rounding
     const int k0 = k & ~1;
@@ -1251,7 +1261,7 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
     st = launch_search(p, img + (size_t)(k - k0) * p->npix * p->npix, 1, nullptr, &gen,
                        stats ? stats + g : nullptr, cand, cap, ncand, s);
     if (st != RF_OK) return st;
-    RF_HIP_TRY(tm->mark(-1));
+    RF_HIP_TRY(tm->mark(-1, s));
   }
   RF_HIP_TRY(tm->flush());
   return RF_OK;

@@ -238,3 +238,34 @@ def test_fused_bright_source_exact_fallback(torch):
     amax = float(np.max(np.abs(im[key])))
     assert abs(s["sigma"] - ref[3]) <= 1.4826 * TOL32 * amax
     assert s["snr"] > 50
+
+
+def test_profile_modes_match_search(torch):
+    """rf_search_segment_profile, serial and concurrent, returns the same
+    candidates as rf_search_segment and times the same launches; a mode other
+    than 0 or 1 is rejected."""
+    import ctypes
+    from paper_1802_03084_amd import _lib
+    p = rfgen.smallcase(nint=24, npix=256, seed=31)
+    say("profile modes")
+    g = gpu_plan(p)
+    dv = upload(p.make_vis())
+    r0, n0, _ = g.search_segment(dv, cap=4096)
+    t1, r1, n1 = g.profile_segment(dv, cap=4096, concurrent=False)
+    t2, r2, n2 = g.profile_segment(dv, cap=4096, concurrent=True)
+    assert n0 == n1 == n2
+    assert np.array_equal(r0, r1) and np.array_equal(r0, r2)
+    for k in ("drs", "grid", "rows", "cols", "select"):
+        assert t1[k][1] == t2[k][1] > 0, k
+        assert t1[k][0] > 0 and t2[k][0] > 0, k
+    kt = _lib.KernelTimes()
+    kt.concurrent = 2
+    ws = g.workspace(_lib.RF_OP_SEGMENT)
+    cand = torch.empty((16, 8), dtype=torch.int32, device=dv.device)
+    ncand = torch.zeros(1, dtype=torch.int32, device=dv.device)
+    st = _lib.load().rf_search_segment_profile(g._h, ctypes.c_void_p(dv.data_ptr()),
+                                               ctypes.c_void_p(cand.data_ptr()), 16,
+                                               ctypes.c_void_p(ncand.data_ptr()), None,
+                                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), None,
+                                               ctypes.byref(kt))
+    assert st == _lib.RF_EINVAL
