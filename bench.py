@@ -54,6 +54,100 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def serving_leg(speedup, nseg, nslots, storage):
+    """The serving workload: three subarrays (A 10 antennas 5 ms, B 19
+    antennas 10 ms, C 27 antennas 5 ms; 10.24 s segments, 256 channels over
+    1.272-1.528 GHz, 64 DMs, widths {1,2,4,8}, 512^2 images) streamed to an
+    rf_server from pinned host memory.  Paced run: each subarray releases a
+    segment every 10.24 / speedup s (phases offset by a third of a period);
+    latency = candidates on the host - release.  Burst run: every segment
+    released at once; sustained rate = data seconds / wall seconds."""
+    import threading
+    import numpy as np
+    import torch
+    import rfgen
+    import paper_1802_03084_amd as rf
+
+    dtype = rf.RF_CF16 if storage == "cf16" else rf.RF_CF32
+    subs = []
+    for name in "ABC":
+        p = rfgen.serving(name)
+        du, dv = p.cell()
+        plan = rf.Plan(p.freq(), p.uvw(), p.tint_s, p.dms, p.widths, p.npix, du, dv, nint=p.nint,
+                       npol=p.npol, vis_dtype=dtype, kdm=p.kdm, threshold=p.threshold)
+        vis = p.make_vis()
+        arr = rfgen.to_cf16(vis) if dtype == rf.RF_CF16 else np.ascontiguousarray(vis)
+        host = torch.from_numpy(arr).pin_memory()
+        del vis, arr
+        subs.append((name, p, plan, host))
+        log(f"serving subarray {name}: {p.nbl} baselines, {p.nint} x {p.tint_s * 1e3:g} ms, "
+            f"{plan.n_images} images per segment")
+    need = [rf.Server.request_bytes(pl, 4096) for _, _, pl, _ in subs]
+    budget = 2 * sum(need)
+    arena = torch.empty(budget, dtype=torch.uint8, device="cuda")
+    srv = rf.Server(arena, nslots=nslots)
+    seg_s = subs[0][1].nint * subs[0][1].tint_s
+
+    def run(schedule):
+        tickets, t0 = [], time.perf_counter()
+
+        def submitter():
+            for t, i in schedule:
+                dt = t0 + t - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                tickets.append((i, srv.submit(subs[i][2], subs[i][3], cap=4096)))
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        out, k = [], 0
+        while k < len(schedule):
+            if k >= len(tickets):
+                time.sleep(0.001)
+                continue
+            i, tk = tickets[k]
+            rows, n, tm = srv.wait(tk)
+            out.append((i, rows, n, tm))
+            k += 1
+        th.join()
+        return out, time.perf_counter() - t0
+
+    for i in range(3):  # first use of each plan, outside the measurement
+        srv.wait(srv.submit(subs[i][2], subs[i][3], cap=4096))
+    period = seg_s / speedup
+    paced = sorted((j * period + i * period / 3, i) for i in range(3) for j in range(nseg))
+    res, wall_p = run(paced)
+    lat = np.array([tm["latency_s"] for _, _, _, tm in res])
+    found = 0
+    for i, rows, n, _ in res:
+        q = subs[i][1].pulses[0]
+        keys = {(int(r["dm_idx"]), int(r["width_idx"]), int(r["t_int"]), int(r["x"]), int(r["y"])) for r in rows}
+        found += (q.dm_idx, q.width_idx, q.t0, q.x, q.y) in keys
+    burst = [(0.0, i) for j in range(nseg) for i in range(3)]
+    resb, wall_b = run(burst)
+    srv.close()
+    imgs = sum(subs[i][2].n_images for i, _, _, _ in resb)
+    out = {
+        "workload": "3 subarrays (10, 19, 27 antennas; 5/10/5 ms; 10.24 s segments), 256 chans "
+                    "1.272-1.528 GHz, 64 DMs, widths [1,2,4,8], 512^2 images, "
+                    f"{storage} storage, pinned host -> device per segment",
+        "slots": nslots, "arena_bytes": budget,
+        "paced": {"speedup_vs_real_time": speedup, "segments": len(res),
+                  "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+                  "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+                  "latency_max_s": round(float(lat.max()), 4),
+                  "per_subarray_p99_s": {subs[i][0]: round(float(np.percentile(
+                      [tm["latency_s"] for j, _, _, tm in res if j == i], 99)), 4) for i in range(3)},
+                  "pulses_recovered": f"{found}/{len(res)}"},
+        "burst": {"segments": len(resb), "wall_s": round(wall_b, 3), "images_per_s": round(imgs / wall_b, 1),
+                  "rtf": round(len(resb) / 3 * seg_s / wall_b, 2)},
+    }
+    log(f"serving paced x{speedup}: p50 {out['paced']['latency_p50_s'] * 1e3:.0f} ms, "
+        f"p99 {out['paced']['latency_p99_s'] * 1e3:.0f} ms over {len(res)} segments; burst "
+        f"{out['burst']['images_per_s']:.0f} images/s, RTF {out['burst']['rtf']} (3 streams)")
+    return out
+
+
 def cpu_baseline(p, vis, n_images_target, procs):
     """The CPU oracle, as it stands, on a bounded sample of the workload's
     images (DM indices spread over the grid x every width x integrations
@@ -120,6 +214,12 @@ def main():
                     help="search only the first K DM trials (short runs for hardware counters)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the event-timed kernel pass (for counter collection)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serving-speedup", type=float, default=8.0,
+                    help="release rate of the paced serving run, in multiples of real time")
+    ap.add_argument("--serving-segments", type=int, default=12, help="segments per subarray")
+    ap.add_argument("--serving-slots", type=int, default=3)
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (a plain copy kernel of known size, "
                          "to scale the HBM byte counters) and report its bandwidth")
@@ -153,6 +253,11 @@ def main():
         dt = t0.elapsed_time(t1) / reps * 1e-3
         print(json.dumps({"copy_bytes": n, "read_plus_write_GBps": round(2 * n / dt / 1e9, 1),
                           "avg_us": round(dt * 1e6, 1)}), flush=True)
+        return
+
+    if args.serving_only:
+        print(json.dumps({"serving": serving_leg(args.serving_speedup, args.serving_segments,
+                                                 args.serving_slots, "cf16")}), flush=True)
         return
 
     p = rfgen.survey() if args.workload == "survey" else rfgen.tiny()
@@ -290,6 +395,12 @@ def main():
         log(f"plain step chain: {tp:.2f}s/step, {plan.n_images / tp:.0f} images/s, same candidates {keys_p == keys}")
         del wsp
 
+    serving = None
+    if not args.no_serving:
+        del ws, dvis
+        torch.cuda.empty_cache()
+        serving = serving_leg(args.serving_speedup, args.serving_segments, args.serving_slots, "cf16")
+
     out = {
         "metric": "images searched/sec",
         "value": round(img_s, 1),
@@ -317,6 +428,7 @@ def main():
         "kernels_serial_avg_us": serial,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -274,6 +274,59 @@ rf_status rf_search_segment_steps(const rf_plan *plan, const void *d_vis, rf_can
                                   int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,
                                   void *d_ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over streamed segments (Law et al. 2018, section
+ * 3.2: the correlator output is cut into independent, overlapping segments
+ * that the search cluster processes as they arrive).  A segment is released
+ * (submitted) when its last integration has arrived; it is admitted when one
+ * of the server's slots is free and its device block fits in the caller's
+ * arena (first fit; among waiting segments the earliest that fits goes
+ * first), copied host to device on the slot's stream, searched with
+ * rf_search_segment, and its candidates are copied back.  Slots run
+ * concurrently, so segments of different plans (shapes) overlap on the device.
+ * ------------------------------------------------------------------------ */
+typedef struct rf_server rf_server;
+
+typedef struct rf_serve_times {
+  double released_s;  /* submission, seconds since the server was created */
+  double started_s;   /* admission                                        */
+  double done_s;      /* candidates on the host                           */
+  double latency_s;   /* done - released                                  */
+} rf_serve_times;
+
+/* Device bytes one request of `plan` with candidate capacity `cap` takes from
+ * the arena: segment copy + rf_workspace_bytes(RF_OP_SEGMENT) + cap rows +
+ * the count, each 256-byte aligned.  RF_EINVAL on NULL, RF_ERANGE if cap < 0. */
+rf_status rf_server_request_bytes(const rf_plan *plan, int32_t cap, size_t *bytes);
+
+/* Starts nslots (1..16) slot threads on the current device, each with its own
+ * stream (default priority).  d_arena: caller-owned device memory of
+ * arena_bytes (256-byte aligned), used until rf_server_destroy returns; the
+ * server allocates no device memory.  RF_EINVAL on NULL, zero size or a
+ * misaligned arena; RF_ERANGE for nslots outside 1..16; RF_EHIP if the
+ * current device cannot be read. */
+rf_status rf_server_create(void *d_arena, size_t arena_bytes, int32_t nslots, rf_server **out);
+
+/* Releases one segment: h_vis is host memory in the plan's segment layout
+ * (pinned memory makes the copy asynchronous); it and the plan must stay
+ * valid until rf_server_wait returns for the ticket.  Returns at once.
+ * RF_EWORKSPACE if the request could never fit in the arena, RF_EINVAL on
+ * NULL arguments or after rf_server_destroy began, RF_ERANGE if cap < 0. */
+rf_status rf_server_submit(rf_server *server, const rf_plan *plan, const void *h_vis, int32_t cap,
+                           int64_t *ticket);
+
+/* Blocks until the ticket's segment is done, then copies min(count, cap)
+ * candidate rows (device order) to h_cand, the true count to *ncand and the
+ * timestamps to *times (nullable); the ticket is then forgotten (a second
+ * wait on it returns RF_EINVAL).  Returns the search's status. */
+rf_status rf_server_wait(rf_server *server, int64_t ticket, rf_candidate *h_cand, int32_t cap,
+                         int32_t *ncand, rf_serve_times *times);
+
+/* Runs every released segment to completion, stops the slots and frees the
+ * server (results not collected are dropped).  Must not overlap other calls
+ * on the same server. */
+rf_status rf_server_destroy(rf_server *server);
+
 #ifdef __cplusplus
 }
 #endif

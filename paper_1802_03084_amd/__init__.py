@@ -24,7 +24,8 @@ from ._lib import (RF_CF16, RF_CF32, RF_OP_IMAGE, RF_OP_SEARCH, RF_OP_SEGMENT,  
                    RF_OP_SEGMENT_STEPS,
                    Candidate, ImageStats, ImageTag, RFError)
 
-__all__ = ["Plan", "RFError", "RF_CF32", "RF_CF16", "load_library", "CAND_DTYPE", "STATS_DTYPE"]
+__all__ = ["Plan", "Server", "RFError", "RF_CF32", "RF_CF16", "load_library", "CAND_DTYPE",
+           "STATS_DTYPE"]
 
 CAND_DTYPE = np.dtype([("dm_idx", "<i4"), ("width_idx", "<i4"), ("t_int", "<i4"), ("x", "<i4"),
                        ("y", "<i4"), ("snr", "<f4"), ("peak", "<f4"), ("sigma", "<f4")])
@@ -263,3 +264,68 @@ class Plan:
         rows = np.sort(rows, order=["dm_idx", "width_idx", "t_int"])
         st = stats.cpu().numpy().view(STATS_DTYPE).reshape(-1) if stats is not None else None
         return rows, n, st
+
+
+class Server:
+    """rf_server_*: segments released to a request loop, admitted by the HBM
+    budget of one device arena and searched concurrently on `nslots` slot
+    streams.  The arena is a caller-owned uint8 device tensor; segments are
+    host tensors in the plan's layout (pinned for asynchronous copies) that
+    must stay alive until their wait returns."""
+
+    def __init__(self, arena, nslots=2):
+        self._arena = arena  # keeps the device memory alive
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().rf_server_create(_ptr(arena), arena.numel() * arena.element_size(),
+                                                int(nslots), ctypes.byref(h)), "rf_server_create")
+        self._h = h
+        self._keep = {}
+
+    @staticmethod
+    def request_bytes(plan, cap=4096):
+        n = ctypes.c_size_t()
+        _lib.check(_lib.load().rf_server_request_bytes(plan.handle, int(cap), ctypes.byref(n)),
+                   "rf_server_request_bytes")
+        return n.value
+
+    def submit(self, plan, h_vis, cap=4096):
+        """Releases one segment; returns its ticket at once."""
+        torch = _torch()
+        want_dt = torch.complex64 if plan.vis_dtype == RF_CF32 else torch.float16
+        want = (plan.nint, plan.nbl, plan.nchan, plan.npol) + (() if want_dt == torch.complex64 else (2,))
+        if h_vis.dtype != want_dt or tuple(h_vis.shape) != want or not h_vis.is_contiguous() \
+                or h_vis.device.type != "cpu":
+            raise ValueError(f"h_vis: expected contiguous host {want_dt} {want}, got {h_vis.dtype} "
+                             f"{tuple(h_vis.shape)} on {h_vis.device}")
+        t = ctypes.c_int64()
+        _lib.check(_lib.load().rf_server_submit(self._h, plan.handle, _ptr(h_vis), int(cap),
+                                                ctypes.byref(t)), "rf_server_submit")
+        self._keep[t.value] = (plan, h_vis, int(cap))
+        return t.value
+
+    def wait(self, ticket):
+        """Blocks until the ticket's segment is done: (rows sorted by (dm_idx,
+        width_idx, t_int), true count, {released_s, started_s, done_s, latency_s})."""
+        plan, h_vis, cap = self._keep.pop(ticket)
+        buf = (Candidate * max(cap, 1))()
+        n = ctypes.c_int32()
+        tm = _lib.ServeTimes()
+        _lib.check(_lib.load().rf_server_wait(self._h, int(ticket), ctypes.cast(buf, ctypes.c_void_p),
+                                              cap, ctypes.byref(n), ctypes.byref(tm)), "rf_server_wait")
+        k = min(n.value, cap)
+        rows = np.frombuffer(bytes(buf)[: k * ctypes.sizeof(Candidate)], dtype=CAND_DTYPE).copy()
+        rows = np.sort(rows, order=["dm_idx", "width_idx", "t_int"])
+        times = {f: getattr(tm, f) for f, _ in _lib.ServeTimes._fields_}
+        return rows, n.value, times
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.load().rf_server_destroy(self._h), "rf_server_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

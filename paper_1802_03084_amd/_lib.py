@@ -72,6 +72,11 @@ class KernelTimes(ctypes.Structure):
 
 KERNEL_KINDS = ["drs", "rows", "cols", "select", "fallback", "grid"]
 
+
+class ServeTimes(ctypes.Structure):
+    _fields_ = [("released_s", ctypes.c_double), ("started_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("latency_s", ctypes.c_double)]
+
 assert ctypes.sizeof(Candidate) == 32
 assert ctypes.sizeof(ImageStats) == 20
 assert ctypes.sizeof(ImageTag) == 12
@@ -95,6 +100,12 @@ SIGNATURES = {
     "rf_search_segment_steps": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_size, c_vp]),
     "rf_search_segment_profile": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_size, c_vp,
                                           ctypes.POINTER(KernelTimes)]),
+    "rf_server_request_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_size)]),
+    "rf_server_create": (c_i32, [c_vp, c_size, c_i32, ctypes.POINTER(c_vp)]),
+    "rf_server_submit": (c_i32, [c_vp, c_vp, c_vp, c_i32, ctypes.POINTER(c_i64)]),
+    "rf_server_wait": (c_i32, [c_vp, c_i64, c_vp, c_i32, ctypes.POINTER(c_i32),
+                               ctypes.POINTER(ServeTimes)]),
+    "rf_server_destroy": (c_i32, [c_vp]),
 }
 
 _lib = None

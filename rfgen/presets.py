@@ -123,5 +123,27 @@ def smallcase(nant=10, nint=37, nchan=48, npix=128, seed=5, npol=2):
                   seed=seed, pulses=[Pulse(dm_idx=1, width_idx=1, t0=4, x=c + 5, y=c - 3)])
 
 
+# Serving subarrays: antennas, integration time, integrations per 10.24 s segment
+SUBARRAYS = {"A": (10, 0.005, 2048), "B": (19, 0.010, 1024), "C": (27, 0.005, 2048)}
+
+
+def serving(sub="C", seed=None):
+    """One segment of a serving subarray: 10.24 s of data, 256 channels over
+    the L band of Table 1 (1.272-1.528 GHz), 2 pols, DM 0-1000 in 64 trials,
+    widths {1,2,4,8}, 512^2 images; one S/N 20 pulse.  Subarrays A (10
+    antennas, 5 ms), B (19, 10 ms), C (27, 5 ms)."""
+    nant, tint, nint = SUBARRAYS[sub]
+    n = 512
+    c = n // 2
+    k = "ABC".index(sub)
+    return Preset(name=f"serving-{sub}", nant=nant, nint=nint, tint_s=tint, f_lo_ghz=1.272,
+                  f_hi_ghz=1.528, nchan=256, npol=2, dms=np.linspace(0, 1000, 64),
+                  widths=[1, 2, 4, 8], npix=n, seed=3 + k if seed is None else seed,
+                  pulses=[Pulse(dm_idx=20 + 9 * k, width_idx=k, t0=64 * (k + 1),
+                                x=c + 11 - 5 * k, y=c - 9 + 4 * k)])
+
+
 def preset_by_name(name):
+    if name.startswith("serving-"):
+        return serving(name.split("-", 1)[1])
     return {"tiny": tiny, "survey": survey, "small": smallcase}[name]()

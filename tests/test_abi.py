@@ -116,3 +116,23 @@ def test_null_arguments_rejected_without_gpu():
     assert L.rf_dedisperse(None, 0, None, None, None) == -1
     assert L.rf_search_segment(None, None, None, 0, None, None, None, 0, None) == -1
     assert L.rf_plan_destroy(None) == 0
+
+
+def test_server_arguments_rejected_without_gpu():
+    """Serving entry points validate on the host before any HIP call."""
+    L = lib()
+    out = ctypes.c_void_p(123)
+    n = ctypes.c_size_t(0)
+    t = ctypes.c_int64(0)
+    k = ctypes.c_int32(0)
+    assert L.rf_server_request_bytes(None, 0, ctypes.byref(n)) == -1
+    assert L.rf_server_create(None, 1 << 20, 2, ctypes.byref(out)) == -1
+    assert out.value is None  # *out cleared on error
+    assert L.rf_server_create(ctypes.c_void_p(4096), 0, 2, ctypes.byref(out)) == -1
+    assert L.rf_server_create(ctypes.c_void_p(4096), 1 << 20, 0, ctypes.byref(out)) == -3
+    assert L.rf_server_create(ctypes.c_void_p(4096), 1 << 20, 17, ctypes.byref(out)) == -3
+    assert L.rf_server_create(ctypes.c_void_p(4097), 1 << 20, 2, ctypes.byref(out)) == -1
+    assert L.rf_server_create(ctypes.c_void_p(4096), 1 << 20, 2, None) == -1
+    assert L.rf_server_submit(None, None, None, 0, ctypes.byref(t)) == -1
+    assert L.rf_server_wait(None, 1, None, 0, ctypes.byref(k), None) == -1
+    assert L.rf_server_destroy(None) == -1
