@@ -104,6 +104,8 @@ typedef struct rf_plan_info {
   int32_t max_delay;    /* largest delay in the table, integrations            */
   int32_t npix;
   size_t table_bytes;   /* bytes of the device table buffer actually used      */
+  int32_t lanes;        /* tuning: lane streams of the fused search            */
+  int32_t m_budget_mb;  /* tuning: all lanes' row-transformed batches, MB      */
 } rf_plan_info;
 
 /* One image's identity: DM trial index, width index, start integration. */
@@ -326,6 +328,53 @@ rf_status rf_server_wait(rf_server *server, int64_t ticket, rf_candidate *h_cand
  * server (results not collected are dropped).  Must not overlap other calls
  * on the same server. */
 rf_status rf_server_destroy(rf_server *server);
+
+/* ------------------------------------------------------------------------
+ * Tuning and batches.
+ * ------------------------------------------------------------------------ */
+
+/* Sets how the fused search schedules its work: `lanes` (1..4) concurrent
+ * batch pipelines (streams) and `m_budget_mb` (16..4096) for the row-
+ * transformed batches of all lanes together (image pairs per batch follow
+ * from it).  Results do not depend on either (the same arithmetic per
+ * image); speed does.  Defaults 2 and 240.  Changes
+ * rf_workspace_bytes(RF_OP_SEGMENT): call before sizing workspaces, and not
+ * while the plan is in use.  RF_EINVAL on NULL, RF_ERANGE out of range. */
+rf_status rf_plan_set_tuning(rf_plan *plan, int32_t lanes, int32_t m_budget_mb);
+
+/* A batch: the fused searches of nseg segments (plans of any shapes) bound
+ * once and run by one rf_batch_run call.  The segments run in order and
+ * share one workspace.  (Graph capture of the batch is switched off: see
+ * rf_batch_run.) */
+typedef struct rf_batch rf_batch;
+
+/* Workspace of a batch over plans[0..nseg): the largest segment workspace
+ * plus one fallback list per segment. */
+rf_status rf_batch_workspace_bytes(const rf_plan *const *plans, int32_t nseg, size_t *bytes);
+
+/* Binds the batch (stream: reserved, may be NULL).
+ * Every buffer is bound now and read or written by every rf_batch_run: per
+ * segment i, d_vis[i] (the plan's segment layout), d_cand[i] (cap[i] rows),
+ * d_ncand[i], d_stats[i] (d_stats may be NULL, or entries NULL); d_ws of
+ * rf_batch_workspace_bytes.  All caller-owned and kept alive until
+ * rf_batch_destroy.  Nothing runs until rf_batch_run.  RF_EINVAL on NULL
+ * arguments or nseg < 1, RF_ERANGE on a negative cap, RF_EWORKSPACE if ws is
+ * too small, RF_EHIP if the batch's streams cannot be created. */
+rf_status rf_batch_create(const rf_plan *const *plans, int32_t nseg, const void *const *d_vis,
+                          rf_candidate *const *d_cand, const int32_t *cap,
+                          int32_t *const *d_ncand, rf_image_stats *const *d_stats, void *d_ws,
+                          size_t ws_bytes, void *stream, rf_batch **out);
+
+/* Enqueues every segment's fused search on `stream` (with the batch's lane
+ * streams: the end of one segment overlaps the start of the next), then
+ * recomputes exactly the images whose median left the bracket (one
+ * synchronisation of `stream` per segment).  Results as rf_search_segment on
+ * each segment.  Capturing the batch into one HIP graph is switched off: its
+ * one run crashed the host process inside the stream capture, with no cause
+ * found in this library's capture sequence. */
+rf_status rf_batch_run(rf_batch *batch, void *stream);
+
+rf_status rf_batch_destroy(rf_batch *batch);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,7 @@ from ._lib import (RF_CF16, RF_CF32, RF_OP_IMAGE, RF_OP_SEARCH, RF_OP_SEGMENT,  
                    RF_OP_SEGMENT_STEPS,
                    Candidate, ImageStats, ImageTag, RFError)
 
-__all__ = ["Plan", "Server", "RFError", "RF_CF32", "RF_CF16", "load_library", "CAND_DTYPE",
+__all__ = ["Plan", "Server", "Batch", "RFError", "RF_CF32", "RF_CF16", "load_library", "CAND_DTYPE",
            "STATS_DTYPE"]
 
 CAND_DTYPE = np.dtype([("dm_idx", "<i4"), ("width_idx", "<i4"), ("t_int", "<i4"), ("x", "<i4"),
@@ -87,6 +87,11 @@ class Plan:
         d.t_begin = int(t_begin)
         d.t_end = self.nint if t_end is None else int(t_end)
         self._desc = d
+        self._args = dict(freq_ghz=self._freq, uvw_m=self._uvw, tint_s=float(tint_s), dms=self._dm,
+                          widths=self._width, npix=self.npix, du=float(du), dv=float(dv),
+                          nint=self.nint, npol=self.npol, vis_dtype=self.vis_dtype, kdm=float(kdm),
+                          threshold=float(threshold), t_begin=int(t_begin), t_end=d.t_end,
+                          device=device)
         nbytes = _lib.c_size(0)
         _lib.check(lib.rf_plan_table_bytes(ctypes.byref(d), ctypes.byref(nbytes)), "rf_plan_table_bytes")
         self.device = torch.device(device)
@@ -114,6 +119,25 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def set_tuning(self, lanes, m_budget_mb):
+        """rf_plan_set_tuning: lane streams and the row-transformed batch
+        budget (MB) of the fused search; results do not depend on them."""
+        _lib.check(_lib.load().rf_plan_set_tuning(self._h, int(lanes), int(m_budget_mb)),
+                   "rf_plan_set_tuning")
+        info = _lib.PlanInfo()
+        _lib.check(_lib.load().rf_plan_query(self._h, ctypes.byref(info)), "rf_plan_query")
+        self.info = {k: getattr(info, k) for k, _ in _lib.PlanInfo._fields_}
+
+    @property
+    def tuning(self):
+        return int(self.info["lanes"]), int(self.info["m_budget_mb"])
+
+    def subplan(self, ndm):
+        """A plan of the same shape over the first ndm DM trials (for tuning)."""
+        args = dict(self._args)
+        args["dms"] = self._dm[: max(1, int(ndm))]
+        return Plan(**args)
 
     def image_base(self, dm_idx, width_idx):
         per_dm = sum(self.nint // w for w in self.widths)
@@ -321,6 +345,62 @@ class Server:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.check(_lib.load().rf_server_destroy(self._h), "rf_server_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """rf_batch_*: the fused searches of several segments (plans of any shapes)
+    bound once and run by one call.  The segment tensors are bound at
+    creation: refill them in place between runs."""
+
+    def __init__(self, plans, vis, cap=4096, with_stats=False, stream=None):
+        torch = _torch()
+        lib = _lib.load()
+        n = len(plans)
+        if n < 1 or len(vis) != n:
+            raise ValueError("one segment tensor per plan")
+        for p, v in zip(plans, vis):
+            p._check_vis(v, p.nint)
+        self.plans, self.vis, self.cap = list(plans), list(vis), int(cap)
+        dev = vis[0].device
+        self.cand = [torch.empty((max(self.cap, 1), 8), dtype=torch.int32, device=dev) for _ in plans]
+        self.ncand = [torch.zeros(1, dtype=torch.int32, device=dev) for _ in plans]
+        self.stats = ([torch.empty((p.n_images, 5), dtype=torch.int32, device=dev) for p in plans]
+                      if with_stats else None)
+        hs = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+        nb = ctypes.c_size_t()
+        _lib.check(lib.rf_batch_workspace_bytes(hs, n, ctypes.byref(nb)), "rf_batch_workspace_bytes")
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        arr = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])  # noqa: E731
+        self._keep = (hs, arr(self.vis), arr(self.cand), (ctypes.c_int32 * n)(*([self.cap] * n)),
+                      arr(self.ncand), arr(self.stats) if self.stats else None)
+        h = ctypes.c_void_p()
+        _lib.check(lib.rf_batch_create(hs, n, self._keep[1], self._keep[2], self._keep[3],
+                                       self._keep[4], self._keep[5], _ptr(self.ws), nb.value,
+                                       _stream(stream), ctypes.byref(h)), "rf_batch_create")
+        self._h = h
+
+    def run(self, stream=None, collect=True):
+        """Runs every segment (then the exact fallbacks); returns per segment
+        (rows sorted by (dm_idx, width_idx, t_int), true count, stats or None)."""
+        _lib.check(_lib.load().rf_batch_run(self._h, _stream(stream)), "rf_batch_run")
+        if not collect:
+            return None
+        out = []
+        for i in range(len(self.plans)):
+            st = self.stats[i] if self.stats else None
+            out.append(Plan._collect(self.cand[i], self.ncand[i], st, self.cap))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.load().rf_batch_destroy(self._h), "rf_batch_destroy")
             self._h = ctypes.c_void_p()
 
     def __del__(self):

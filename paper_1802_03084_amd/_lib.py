@@ -47,6 +47,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [
         ("n_images", c_i64), ("n_valid", c_i32), ("n_dropped", c_i32), ("n_cells", c_i32),
         ("n_rows", c_i32), ("max_delay", c_i32), ("npix", c_i32), ("table_bytes", c_size),
+        ("lanes", c_i32), ("m_budget_mb", c_i32),
     ]
 
 
@@ -106,6 +107,12 @@ SIGNATURES = {
     "rf_server_wait": (c_i32, [c_vp, c_i64, c_vp, c_i32, ctypes.POINTER(c_i32),
                                ctypes.POINTER(ServeTimes)]),
     "rf_server_destroy": (c_i32, [c_vp]),
+    "rf_plan_set_tuning": (c_i32, [c_vp, c_i32, c_i32]),
+    "rf_batch_workspace_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_size)]),
+    "rf_batch_create": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp,
+                                ctypes.POINTER(c_vp)]),
+    "rf_batch_run": (c_i32, [c_vp, c_vp]),
+    "rf_batch_destroy": (c_i32, [c_vp]),
 }
 
 _lib = None

@@ -32,7 +32,7 @@ namespace {
 
 using namespace rf;
 
-constexpr int kLanes = 2;              // concurrent batch pipelines (streams) of a segment search
+constexpr int kMaxLanes = 4;           // concurrent batch pipelines (streams) of a segment search
 constexpr int kMaxW = 8;               // widths handled by one pass over the segment
 constexpr float kMedOverRms = 0.6745f; // median |x| / rms of a zero-mean Gaussian
 // half-width of the median bracket (relative): the bracket holds about 0.86%
@@ -853,10 +853,12 @@ Shape shape_n(const rf_plan *p) {
   s.capb = ColCfg<N>::COLS * N / 16;
   static_assert(N / ColCfg<N>::COLS <= kMaxCB, "column workgroups per image");
   static_assert(ColCfg<N>::COLS * N / 16 >= 128, "a list region holds the staged 128 values");
-  // pairs per batch: the row-transformed batches of all lanes (~240 MB)
-  // stay resident in the last-level cache between the row and column passes
+  // pairs per batch: the row-transformed batches of all lanes (the plan's
+  // budget, 240 MB by default) stay resident in the last-level cache between
+  // the row and column passes
   const size_t per_pair = (size_t)std::max(1, p->n_rows) * N * sizeof(float2);
-  const int pb = (int)std::max<size_t>(s.pbw, ((size_t)240 << 20) / kLanes / per_pair);
+  const int pb = (int)std::max<size_t>(
+      s.pbw, ((size_t)p->m_budget_mb << 20) / (size_t)p->lanes / per_pair);
   s.pb = std::min(64, (pb / s.pbw) * s.pbw);
   return s;
 }
@@ -881,7 +883,7 @@ struct LaneBufs {
 // that the next DM's pass over the segment overlaps this DM's batches.
 struct Layout {
   size_t vi[2], fb, dd, rs, grid, img, mws, total;
-  LaneBufs lane[kLanes];
+  LaneBufs lane[kMaxLanes];
   std::vector<size_t> vi_off;  // per width, in float2 units
 };
 
@@ -901,7 +903,7 @@ Layout layout_of(const rf_plan *p) {
     return at;
   };
   for (int d = 0; d < 2; ++d) L.vi[d] = take(vi_elems * sizeof(float2));
-  for (int k = 0; k < kLanes; ++k) {
+  for (int k = 0; k < p->lanes; ++k) {
     LaneBufs &b = L.lane[k];
     b.cv = take((size_t)2 * sh.pb * std::max(1, p->n_cells) * sizeof(float2));
     b.m = take((size_t)sh.pb * p->n_rows * p->npix * sizeof(float2));
@@ -971,22 +973,24 @@ struct Timer {
     RF_HIP_TRY((tm)->mark(-1, s));       \
   } while (0)
 
-// Streams and events of a segment search: kLanes lane streams, a stream for
-// the per-DM pass over the segment, and the events ordering them.  Created
-// per call, default priority.
+// Streams and events of a segment search: lane streams, a stream for the
+// per-DM pass over the segment, and the events ordering them; default
+// priority.  Created per call, or once per batch (kept until the batch's
+// graph is destroyed).
 struct Lanes {
-  hipStream_t lane[kLanes] = {}, drs = nullptr;
-  hipEvent_t start = nullptr, drs_done[2] = {}, lane_dm[kLanes][2] = {}, lane_end[kLanes] = {};
+  hipStream_t lane[kMaxLanes] = {}, drs = nullptr;
+  hipEvent_t start = nullptr, drs_done[2] = {}, lane_dm[kMaxLanes][2] = {},
+             lane_end[kMaxLanes] = {};
   hipError_t init() {
     hipError_t e = hipStreamCreateWithFlags(&drs, hipStreamNonBlocking);
-    for (int k = 0; k < kLanes && e == hipSuccess; ++k)
+    for (int k = 0; k < kMaxLanes && e == hipSuccess; ++k)
       e = hipStreamCreateWithFlags(&lane[k], hipStreamNonBlocking);
     auto ev = [&](hipEvent_t &x) {
       if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
     };
     ev(start);
     for (int d = 0; d < 2; ++d) ev(drs_done[d]);
-    for (int k = 0; k < kLanes; ++k) {
+    for (int k = 0; k < kMaxLanes; ++k) {
       ev(lane_dm[k][0]);
       ev(lane_dm[k][1]);
       ev(lane_end[k]);
@@ -999,7 +1003,7 @@ struct Lanes {
     };
     de(start);
     for (int d = 0; d < 2; ++d) de(drs_done[d]);
-    for (int k = 0; k < kLanes; ++k) {
+    for (int k = 0; k < kMaxLanes; ++k) {
       de(lane_dm[k][0]);
       de(lane_dm[k][1]);
       de(lane_end[k]);
@@ -1126,18 +1130,16 @@ size_t segment_ws_bytes(const rf_plan *p) {
   return layout_of(p).total;
 }
 
-rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
-                      int32_t *ncand, rf_image_stats *stats, void *ws_v, size_t ws_bytes,
-                      hipStream_t s, rf_kernel_times *kt) {
-  Timer timer;
-  timer.kt = kt;
-  timer.streams.push_back(s);
-  Timer *tm = &timer;
-  char *ws = static_cast<char *>(ws_v);
+// Enqueues the fused search of one segment on stream s and the lane streams
+// of `lanes` (joined to s at the end): no host synchronisation, so a batch can
+// capture it into a graph.  The images whose median left the bracket are
+// listed in fb ([0] = count, then global image indices) for segment_finish.
+// serial: every launch in order on s (timed kernels that do not overlap).
+rf_status segment_enqueue(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
+                          int32_t *ncand, rf_image_stats *stats, char *ws, size_t ws_bytes,
+                          int32_t *fb, hipStream_t s, Lanes *lanes, bool serial, Timer *tm) {
   const Layout L = layout_of(p);
   const Shape sh = shape_of(p);
-  const size_t nbc = (size_t)p->nbl * p->nchan;
-  int32_t *fb = (int32_t *)(ws + L.fb);
   rf_status st = launch_zero_i32(ncand, 1, s);
   if (st != RF_OK) return st;
   st = launch_zero_i32(fb, 1, s);
@@ -1147,29 +1149,25 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
     // produces the (zero) statistics
     return run_segment_steps(p, vis, cand, cap, ncand, stats, ws, ws_bytes, s);
   }
-  // kLanes lane streams take the batches round robin and a stream of its own
+  // The lane streams take the batches round robin and a stream of its own
   // runs each DM's pass over the segment into the sample buffer of that DM's
   // parity.  The pass of DM i waits until every lane has finished the batches
   // of DM i - 2 (the last readers of that buffer); a lane's batches of DM i
-  // wait for the pass of DM i.  Timed serially: everything in order on the
-  // caller's stream, so that kernel durations do not overlap.
-  const bool serial = kt && !kt->concurrent;
-  Lanes lanes;
-  const int nl = serial ? 1 : kLanes;
-  hipStream_t ls[kLanes], ds = s;
-  for (int k = 0; k < kLanes; ++k) ls[k] = s;
+  // wait for the pass of DM i.
+  const int nl = serial ? 1 : p->lanes;
+  hipStream_t ls[kMaxLanes], ds = s;
+  for (int k = 0; k < kMaxLanes; ++k) ls[k] = s;
   if (!serial) {
-    RF_HIP_TRY(lanes.init());
-    RF_HIP_TRY(hipEventRecord(lanes.start, s));
-    RF_HIP_TRY(hipStreamWaitEvent(lanes.drs, lanes.start, 0));
-    ds = lanes.drs;
-    for (int k = 0; k < kLanes; ++k) {
-      ls[k] = lanes.lane[k];
-      RF_HIP_TRY(hipStreamWaitEvent(ls[k], lanes.start, 0));
+    RF_HIP_TRY(hipEventRecord(lanes->start, s));
+    RF_HIP_TRY(hipStreamWaitEvent(lanes->drs, lanes->start, 0));
+    ds = lanes->drs;
+    for (int k = 0; k < nl; ++k) {
+      ls[k] = lanes->lane[k];
+      RF_HIP_TRY(hipStreamWaitEvent(ls[k], lanes->start, 0));
     }
     // the caller's stream stays in the list: the exact fallback records there
-    timer.streams.insert(timer.streams.end(), ls, ls + kLanes);
-    timer.streams.push_back(ds);
+    tm->streams.insert(tm->streams.end(), ls, ls + nl);
+    tm->streams.push_back(ds);
   }
   int nbatch = 0;
   std::vector<float2 *> vi_out(p->nwidth);
@@ -1177,13 +1175,14 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
     float2 *vi = (float2 *)(ws + L.vi[i & 1]);
     for (int j = 0; j < p->nwidth; ++j) vi_out[j] = vi + L.vi_off[j];
     if (!serial && i >= 2)
-      for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipStreamWaitEvent(ds, lanes.lane_dm[k][i & 1], 0));
+      for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipStreamWaitEvent(ds, lanes->lane_dm[k][i & 1], 0));
     st = drs_timed(p, p->d_delay + (size_t)i * p->nchan, vis, p->width.data(), p->nwidth,
                    vi_out.data(), ds, tm);
     if (st != RF_OK) return st;
     if (!serial) {
-      RF_HIP_TRY(hipEventRecord(lanes.drs_done[i & 1], ds));
-      for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipStreamWaitEvent(ls[k], lanes.drs_done[i & 1], 0));
+      RF_HIP_TRY(hipEventRecord(lanes->drs_done[i & 1], ds));
+      for (int k = 0; k < nl; ++k)
+        RF_HIP_TRY(hipStreamWaitEvent(ls[k], lanes->drs_done[i & 1], 0));
     }
     for (int j = 0; j < p->nwidth; ++j) {
       const int w = p->width[j];
@@ -1200,19 +1199,30 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
       }
     }
     if (!serial)
-      for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipEventRecord(lanes.lane_dm[k][i & 1], ls[k]));
+      for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipEventRecord(lanes->lane_dm[k][i & 1], ls[k]));
     // timed serially: flush every DM; timed concurrently: only when the event
     // pool is large (a flush drains the lanes)
-    if (serial || tm->full()) RF_HIP_TRY(tm->flush());
+    if (tm->kt && (serial || tm->full())) RF_HIP_TRY(tm->flush());
   }
   if (!serial) {  // join: the caller's stream waits for every lane
     for (int k = 0; k < nl; ++k) {
-      RF_HIP_TRY(hipEventRecord(lanes.lane_end[k], ls[k]));
-      RF_HIP_TRY(hipStreamWaitEvent(s, lanes.lane_end[k], 0));
+      RF_HIP_TRY(hipEventRecord(lanes->lane_end[k], ls[k]));
+      RF_HIP_TRY(hipStreamWaitEvent(s, lanes->lane_end[k], 0));
     }
   }
-  RF_HIP_TRY(tm->flush());
-  // exact fallback for the images whose median left the bracket
+  return RF_OK;
+}
+
+// Exact fallback of the images listed in fb: reads the list (one host
+// synchronisation of s) and recomputes each listed image with the step chain
+// (paired with its partner image, for identical rounding), replacing its
+// statistics and adding its candidate.
+rf_status segment_finish(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
+                         int32_t *ncand, rf_image_stats *stats, char *ws, const int32_t *fb,
+                         hipStream_t s, Timer *tm) {
+  const Layout L = layout_of(p);
+  const size_t nbc = (size_t)p->nbl * p->nchan;
+  rf_status st = RF_OK;
   int32_t nfb = 0;
   RF_HIP_TRY(hipMemcpyAsync(&nfb, fb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   RF_HIP_TRY(hipStreamSynchronize(s));
@@ -1249,8 +1259,6 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
       cur_j = j;
     }
     RF_HIP_TRY(tm->mark(RF_K_FALLBACK, s));
-    // image the pair the fused path used (2m, 2m+1): two real images share a
-    // complex transform, so the partner is needed for identical rounding
     const int k0 = k & ~1;
     const int npair = std::min(2, p->nint / w - k0);
     st = launch_grid_dense(p, rs + (size_t)k0 * per_int, npair, grid, s);
@@ -1263,6 +1271,110 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
     if (st != RF_OK) return st;
     RF_HIP_TRY(tm->mark(-1, s));
   }
-  RF_HIP_TRY(tm->flush());
   return RF_OK;
 }
+
+rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
+                      int32_t *ncand, rf_image_stats *stats, void *ws_v, size_t ws_bytes,
+                      hipStream_t s, rf_kernel_times *kt) {
+  Timer timer;
+  timer.kt = kt;
+  timer.streams.push_back(s);
+  char *ws = static_cast<char *>(ws_v);
+  int32_t *fb = (int32_t *)(ws + layout_of(p).fb);
+  const bool serial = kt && !kt->concurrent;
+  Lanes lanes;
+  if (!serial) RF_HIP_TRY(lanes.init());
+  rf_status st =
+      segment_enqueue(p, vis, cand, cap, ncand, stats, ws, ws_bytes, fb, s, &lanes, serial, &timer);
+  if (st != RF_OK) return st;
+  RF_HIP_TRY(timer.flush());
+  st = segment_finish(p, vis, cand, cap, ncand, stats, ws, fb, s, &timer);
+  if (st != RF_OK) return st;
+  RF_HIP_TRY(timer.flush());
+  return RF_OK;
+}
+
+// ------------------------------------------------------------------ batches
+// A batch searches several segments (plans of any shapes) bound once: the
+// segments run in order, sharing one workspace, each with its own fallback
+// list.  rf_batch_run enqueues every segment's fused search (the lane
+// streams overlap within a segment and across the boundary into the next),
+// then runs the exact fallbacks.
+//
+// Graph capture of the batch is switched off: its one run (stream capture of
+// the caller's stream with the lane and per-DM streams joined by events,
+// mode relaxed) ended the host process with a segmentation fault inside the
+// capture, and reading the capture sequence found no cause (every captured
+// operation is a kernel launch, every event is recorded inside the capture
+// before it is waited on, every forked stream joins back).  Until a cause is
+// shown, batches run eagerly.
+struct rf_batch {
+  std::vector<const rf_plan *> plans;
+  std::vector<const void *> vis;
+  std::vector<rf_candidate *> cand;
+  std::vector<int32_t> cap;
+  std::vector<int32_t *> ncand;
+  std::vector<rf_image_stats *> stats;
+  std::vector<int32_t *> fb;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  Lanes lanes;
+};
+
+size_t batch_ws_bytes(const rf_plan *const *plans, int nseg, size_t *main_bytes) {
+  size_t m = 0, f = 0;
+  for (int i = 0; i < nseg; ++i) {
+    m = std::max(m, segment_ws_bytes(plans[i]));
+    f += align_up(((size_t)plans[i]->n_images + 1) * sizeof(int32_t));
+  }
+  if (main_bytes) *main_bytes = align_up(m);
+  return align_up(m) + f;
+}
+
+rf_status batch_create(const rf_plan *const *plans, int nseg, const void *const *d_vis,
+                       rf_candidate *const *d_cand, const int32_t *cap, int32_t *const *d_ncand,
+                       rf_image_stats *const *d_stats, void *d_ws, size_t ws_bytes, hipStream_t,
+                       rf_batch **out) {
+  size_t main_bytes = 0;
+  if (ws_bytes < batch_ws_bytes(plans, nseg, &main_bytes)) return RF_EWORKSPACE;
+  rf_batch *b = new rf_batch();
+  b->ws = (char *)d_ws;
+  b->ws_bytes = main_bytes;
+  size_t off = main_bytes;
+  for (int i = 0; i < nseg; ++i) {
+    b->plans.push_back(plans[i]);
+    b->vis.push_back(d_vis[i]);
+    b->cand.push_back(d_cand[i]);
+    b->cap.push_back(cap[i]);
+    b->ncand.push_back(d_ncand[i]);
+    b->stats.push_back(d_stats ? d_stats[i] : nullptr);
+    b->fb.push_back((int32_t *)(b->ws + off));
+    off += align_up(((size_t)plans[i]->n_images + 1) * sizeof(int32_t));
+  }
+  if (b->lanes.init() != hipSuccess) {
+    delete b;
+    return RF_EHIP;
+  }
+  *out = b;
+  return RF_OK;
+}
+
+rf_status batch_run(rf_batch *b, hipStream_t s) {
+  Timer none;
+  none.streams.push_back(s);
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    const rf_status st =
+        segment_enqueue(b->plans[i], b->vis[i], b->cand[i], b->cap[i], b->ncand[i], b->stats[i],
+                        b->ws, b->ws_bytes, b->fb[i], s, &b->lanes, false, &none);
+    if (st != RF_OK) return st;
+  }
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    const rf_status st = segment_finish(b->plans[i], b->vis[i], b->cand[i], b->cap[i], b->ncand[i],
+                                        b->stats[i], b->ws, b->fb[i], s, &none);
+    if (st != RF_OK) return st;
+  }
+  return RF_OK;
+}
+
+void batch_destroy(rf_batch *b) { delete b; }

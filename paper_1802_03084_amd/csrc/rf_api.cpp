@@ -389,6 +389,51 @@ rf_status rf_plan_query(const rf_plan *p, rf_plan_info *info) {
   info->max_delay = p->max_delay;
   info->npix = p->npix;
   info->table_bytes = p->table_bytes;
+  info->lanes = p->lanes;
+  info->m_budget_mb = p->m_budget_mb;
+  return RF_OK;
+}
+
+rf_status rf_plan_set_tuning(rf_plan *p, int32_t lanes, int32_t m_budget_mb) {
+  if (!p) return RF_EINVAL;
+  if (lanes < 1 || lanes > 4 || m_budget_mb < 16 || m_budget_mb > 4096) return RF_ERANGE;
+  p->lanes = lanes;
+  p->m_budget_mb = m_budget_mb;
+  return RF_OK;
+}
+
+rf_status rf_batch_workspace_bytes(const rf_plan *const *plans, int32_t nseg, size_t *bytes) {
+  if (!plans || !bytes || nseg < 1) return RF_EINVAL;
+  for (int i = 0; i < nseg; ++i)
+    if (!plans[i]) return RF_EINVAL;
+  *bytes = batch_ws_bytes(plans, nseg, nullptr);
+  return RF_OK;
+}
+
+rf_status rf_batch_create(const rf_plan *const *plans, int32_t nseg, const void *const *d_vis,
+                          rf_candidate *const *d_cand, const int32_t *cap,
+                          int32_t *const *d_ncand, rf_image_stats *const *d_stats, void *d_ws,
+                          size_t ws_bytes, void *stream, rf_batch **out) {
+  if (!out) return RF_EINVAL;
+  *out = nullptr;
+  if (!plans || nseg < 1 || !d_vis || !d_cand || !cap || !d_ncand || !d_ws) return RF_EINVAL;
+  for (int i = 0; i < nseg; ++i) {
+    if (!plans[i] || !d_vis[i] || !d_ncand[i]) return RF_EINVAL;
+    if (cap[i] < 0) return RF_ERANGE;
+    if (cap[i] > 0 && !d_cand[i]) return RF_EINVAL;
+  }
+  return batch_create(plans, nseg, d_vis, d_cand, cap, d_ncand, d_stats, d_ws, ws_bytes,
+                      (hipStream_t)stream, out);
+}
+
+rf_status rf_batch_run(rf_batch *b, void *stream) {
+  if (!b) return RF_EINVAL;
+  return batch_run(b, (hipStream_t)stream);
+}
+
+rf_status rf_batch_destroy(rf_batch *b) {
+  if (!b) return RF_EINVAL;
+  batch_destroy(b);
   return RF_OK;
 }
 

@@ -18,6 +18,9 @@ struct rf_plan {
   int32_t t_begin, t_end;
   std::vector<double> freq, uvw, dm;
   std::vector<int32_t> width;
+  // tuning of the fused search (rf_plan_set_tuning): lane streams and the
+  // budget of all lanes' row-transformed batches, MB
+  int32_t lanes = 2, m_budget_mb = 240;
 
   // derived
   int32_t W;          // valid (baseline, channel) pairs
@@ -121,3 +124,10 @@ rf_status run_segment_steps(const rf_plan *p, const void *vis, rf_candidate *can
 rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
                       int32_t *ncand, rf_image_stats *stats, void *ws, size_t ws_bytes,
                       hipStream_t s, rf_kernel_times *kt);
+size_t batch_ws_bytes(const rf_plan *const *plans, int nseg, size_t *main_bytes);
+rf_status batch_create(const rf_plan *const *plans, int nseg, const void *const *d_vis,
+                       rf_candidate *const *d_cand, const int32_t *cap, int32_t *const *d_ncand,
+                       rf_image_stats *const *d_stats, void *d_ws, size_t ws_bytes, hipStream_t s,
+                       rf_batch **out);
+rf_status batch_run(rf_batch *b, hipStream_t s);
+void batch_destroy(rf_batch *b);

@@ -136,3 +136,16 @@ def test_server_arguments_rejected_without_gpu():
     assert L.rf_server_submit(None, None, None, 0, ctypes.byref(t)) == -1
     assert L.rf_server_wait(None, 1, None, 0, ctypes.byref(k), None) == -1
     assert L.rf_server_destroy(None) == -1
+
+
+def test_tuning_and_batch_arguments_rejected_without_gpu():
+    L = lib()
+    out = ctypes.c_void_p(123)
+    n = ctypes.c_size_t(0)
+    assert L.rf_plan_set_tuning(None, 2, 240) == -1
+    assert L.rf_batch_workspace_bytes(None, 1, ctypes.byref(n)) == -1
+    assert L.rf_batch_create(None, 1, None, None, None, None, None, None, 0, None,
+                             ctypes.byref(out)) == -1
+    assert out.value is None
+    assert L.rf_batch_run(None, None) == -1
+    assert L.rf_batch_destroy(None) == -1
