@@ -312,10 +312,13 @@ rf_status rf_server_create(void *d_arena, size_t arena_bytes, int32_t nslots, rf
 /* Releases one segment: h_vis is host memory in the plan's segment layout
  * (pinned memory makes the copy asynchronous); it and the plan must stay
  * valid until rf_server_wait returns for the ticket.  Returns at once.
- * RF_EWORKSPACE if the request could never fit in the arena, RF_EINVAL on
- * NULL arguments or after rf_server_destroy began, RF_ERANGE if cap < 0. */
+ * flags: 0, or RF_SERVE_SUBTRACT_MEAN to run rf_subtract_mean on the device
+ * copy before the search.  RF_EWORKSPACE if the request could never fit in
+ * the arena, RF_EINVAL on NULL arguments, unknown flags or after
+ * rf_server_destroy began, RF_ERANGE if cap < 0. */
+enum { RF_SERVE_SUBTRACT_MEAN = 1 };
 rf_status rf_server_submit(rf_server *server, const rf_plan *plan, const void *h_vis, int32_t cap,
-                           int64_t *ticket);
+                           int32_t flags, int64_t *ticket);
 
 /* Blocks until the ticket's segment is done, then copies min(count, cap)
  * candidate rows (device order) to h_cand, the true count to *ncand and the
@@ -328,6 +331,17 @@ rf_status rf_server_wait(rf_server *server, int64_t ticket, rf_candidate *h_cand
  * server (results not collected are dropped).  Must not overlap other calls
  * on the same server. */
 rf_status rf_server_destroy(rf_server *server);
+
+/*
+ * rf_subtract_mean (section 3.1: the mean visibility in time is subtracted on
+ * timescales below the fringe rate, removing constant sources; section 3.2:
+ * a segment is about that long): in place on d_vis (the plan's segment
+ * layout and storage type), every (baseline, channel, polarisation) value
+ * loses its mean over the segment's nint integrations (summed in float64,
+ * subtracted in float32; CF16 storage rounded back to nearest even).
+ * Asynchronous on `stream`.  RF_EINVAL on NULL.
+ */
+rf_status rf_subtract_mean(const rf_plan *plan, void *d_vis, void *stream);
 
 /* ------------------------------------------------------------------------
  * Tuning and batches.

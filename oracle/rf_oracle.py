@@ -23,6 +23,8 @@ Functions and the passages they follow:
   image         section 3.1 / 3.2 (2-D FFT imaging)
   image_stats   section 3.1 (point sources above an S/N threshold, ~6 sigma)
   search        section 3.1 / Figure 2 (the whole loop)
+  subtract_mean section 3.1 (mean visibility subtracted on timescales below
+                the fringe rate), 3.2 (segments of about that length)
 
 Parity pins live in tests/test_oracle_*.py; every function above is pinned
 there against closed forms, brute force, library special cases or the values
@@ -104,6 +106,25 @@ def valid_cells(iu, iv, npix):
     """A (baseline, channel) pair is imaged iff |iu|, |iv| <= N/2 - 1."""
     lim = npix // 2 - 1
     return (np.abs(iu) <= lim) & (np.abs(iv) <= lim)
+
+
+def subtract_mean(vis):
+    """Mean-visibility subtraction over one segment (section 3.1: the mean
+    visibility in time is subtracted on timescales shorter than the fringe
+    rate, which removes constant sources; section 3.2: segments are about
+    that long).
+
+    out[t, b, c, p] = vis[t, b, c, p] - (1/T) sum_t' vis[t', b, c, p].
+    Reading: the mean is taken over the whole segment, per baseline, channel
+    and polarisation, and subtracted from every integration of it (the paper
+    gives the time scale, not the window).  complex128.
+    """
+    v = np.asarray(vis).astype(np.complex128)
+    T = v.shape[0]
+    total = np.zeros(v.shape[1:], dtype=np.complex128)
+    for t in range(T):
+        total += v[t]
+    return v - (total / T)[None]
 
 
 def dedisperse(vis, delay_row):

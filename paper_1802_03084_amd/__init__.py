@@ -120,6 +120,14 @@ class Plan:
     def handle(self):
         return self._h
 
+    def subtract_mean(self, vis, stream=None):
+        """rf_subtract_mean: in place, each (baseline, channel, polarisation)
+        value loses its mean over the segment."""
+        self._check_vis(vis, self.nint)
+        _lib.check(_lib.load().rf_subtract_mean(self._h, _ptr(vis), _stream(stream)),
+                   "rf_subtract_mean")
+        return vis
+
     def set_tuning(self, lanes, m_budget_mb):
         """rf_plan_set_tuning: lane streams and the row-transformed batch
         budget (MB) of the fused search; results do not depend on them."""
@@ -312,8 +320,9 @@ class Server:
                    "rf_server_request_bytes")
         return n.value
 
-    def submit(self, plan, h_vis, cap=4096):
-        """Releases one segment; returns its ticket at once."""
+    def submit(self, plan, h_vis, cap=4096, subtract_mean=False):
+        """Releases one segment; returns its ticket at once.  subtract_mean:
+        the segment's time mean is subtracted on the device before the search."""
         torch = _torch()
         want_dt = torch.complex64 if plan.vis_dtype == RF_CF32 else torch.float16
         want = (plan.nint, plan.nbl, plan.nchan, plan.npol) + (() if want_dt == torch.complex64 else (2,))
@@ -323,7 +332,8 @@ class Server:
                              f"{tuple(h_vis.shape)} on {h_vis.device}")
         t = ctypes.c_int64()
         _lib.check(_lib.load().rf_server_submit(self._h, plan.handle, _ptr(h_vis), int(cap),
-                                                ctypes.byref(t)), "rf_server_submit")
+                                                1 if subtract_mean else 0, ctypes.byref(t)),
+                   "rf_server_submit")
         self._keep[t.value] = (plan, h_vis, int(cap))
         return t.value
 

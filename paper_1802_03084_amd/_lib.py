@@ -103,11 +103,12 @@ SIGNATURES = {
                                           ctypes.POINTER(KernelTimes)]),
     "rf_server_request_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_size)]),
     "rf_server_create": (c_i32, [c_vp, c_size, c_i32, ctypes.POINTER(c_vp)]),
-    "rf_server_submit": (c_i32, [c_vp, c_vp, c_vp, c_i32, ctypes.POINTER(c_i64)]),
+    "rf_server_submit": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, ctypes.POINTER(c_i64)]),
     "rf_server_wait": (c_i32, [c_vp, c_i64, c_vp, c_i32, ctypes.POINTER(c_i32),
                                ctypes.POINTER(ServeTimes)]),
     "rf_server_destroy": (c_i32, [c_vp]),
     "rf_plan_set_tuning": (c_i32, [c_vp, c_i32, c_i32]),
+    "rf_subtract_mean": (c_i32, [c_vp, c_vp, c_vp]),
     "rf_batch_workspace_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_size)]),
     "rf_batch_create": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp,
                                 ctypes.POINTER(c_vp)]),

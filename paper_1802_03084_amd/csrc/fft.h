@@ -349,6 +349,17 @@ __device__ __forceinline__ void fft_rest_blocks(float2 *buf, const float2 *__res
   }
 }
 
+// The last pass of fft_rest_blocks once more (buf still holds its input: the
+// last pass only reads it), handing the same butterflies to consume.
+template <class Sh, int F, int NT, int S, bool JF, bool PRE, class Consume>
+__device__ __forceinline__ void fft_last_again(const float2 *buf, const float2 *__restrict__ tw,
+                                               int tid, Consume consume) {
+  if constexpr (Sh::R2 == 1)
+    fft_last_block<Sh, Sh::R1, Sh::R0, F, NT, S, JF, !PRE>(buf, tw, tid, consume);
+  else
+    fft_last_block<Sh, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF, true>(buf, tw, tid, consume);
+}
+
 // Inverse (exp(+i)) unnormalised FFT of F sequences of length N: inputs from
 // load(f, i), outputs to store(f, k, value), LDS buf of F * S elements
 // (S >= Sh::PADDED) for the exchanges between passes.
@@ -364,9 +375,10 @@ __device__ __forceinline__ void fft_inverse(float2 *buf, const float2 *__restric
   }
 }
 
-// Z value of the paired Hermitian transform at grid position (v, u):
-//   Z = s/2 [G_a(v,u) + conj G_a(-v,-u) + i (G_b(v,u) + conj G_b(-v,-u))]
-// with s = (-1)^(u+v) and sg = s/2.  Evaluated as the (v,u) term plus the
+// Z value of the paired Hermitian transform at grid position (v, u), with the
+// image normalisation folded in:
+//   Z = s/(2W) [G_a(v,u) + conj G_a(-v,-u) + i (G_b(v,u) + conj G_b(-v,-u))]
+// with s = (-1)^(u+v) and sg = s/(2W).  Evaluated as the (v,u) term plus the
 // mirrored term in this fixed order, so that every caller (dense grids or
 // gathered cells) produces bit-identical values.
 __device__ __forceinline__ float2 zval(float2 a, float2 am, float2 b, float2 bm, float sg) {
@@ -405,7 +417,11 @@ struct ColCfg {  // columns: COLS columns per workgroup (~70 KB LDS: two workgro
   static constexpr int COLS = N >= 2048 ? 4 : (N >= 1024 ? 8 : (N >= 512 ? 16 : 32 < N ? 32 : N));
   static constexpr int FIRST = COLS * N / ColFft<N>::R0;  // first-pass butterflies
   static constexpr int NT = N >= 512 ? 512 : (FIRST < 256 ? 256 : FIRST);
-  static constexpr int STRIDE = ColFft<N>::PADDED + 1;  // odd: neighbouring columns on other banks
+  // Columns vary fastest across lanes: a 64-bit LDS access serves 16 lanes
+  // per cycle (COLS columns x 16/COLS butterflies), whose slots f STRIDE +
+  // 17 j + r (first pass; the other passes alike) fall on distinct 8-byte
+  // banks when STRIDE = 16/COLS modulo 16 (PADDED is a multiple of 16).
+  static constexpr int STRIDE = ColFft<N>::PADDED + (COLS < 16 ? 16 / COLS : 1);
 };
 
 }  // namespace rf

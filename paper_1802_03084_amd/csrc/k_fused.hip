@@ -263,8 +263,8 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
     const int32_t *__restrict__ rp_row, const int32_t *__restrict__ rp_sa,
     const int32_t *__restrict__ rp_sb, int n_rp, int n_rows, const int32_t *__restrict__ zs_off,
     const int32_t *__restrict__ zs_u, const int32_t *__restrict__ zs_ck,
-    const int32_t *__restrict__ zs_cmk, const float2 *__restrict__ tw, float2 *__restrict__ M,
-    float *__restrict__ epart) {
+    const int32_t *__restrict__ zs_cmk, float hw, const float2 *__restrict__ tw,
+    float2 *__restrict__ M, float *__restrict__ epart) {
   constexpr int PBW = RowPairCfg<N>::PBW, F = RowPairCfg<N>::F, NT = RowPairCfg<N>::NT;
   constexpr int S = RowPairCfg<N>::STRIDE, PS = RowFft<N>::PS;
   __shared__ float2 buf[F * S];
@@ -280,30 +280,45 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
   __syncthreads();
   const int z0 = zs_off[rp], nz = zs_off[rp + 1] - z0;
   const float ew = two ? 0.5f : 0.25f;  // |H|^2 = |.|^2/4, counted twice for a row pair
+  float e_acc[2 * PBW];                 // this thread's share of each image's energy
+#pragma unroll
+  for (int q = 0; q < 2 * PBW; ++q) e_acc[q] = 0.f;
   for (int it = tid; it < nz * PBW; it += NT) {
     const int z = z0 + it % nz, pp = it / nz;  // positions fastest: contiguous cells
     const int pl = pb0 + pp;
     if (pl >= pbn) continue;
-    const int ia = 2 * (p0 + pl);
-    const bool hasb = ia + 1 < nk;
-    const int ib = 2 * pl;  // image a within the batch
+    const bool hasb = 2 * (p0 + pl) + 1 < nk;
     const int u = zs_u[z], ck = zs_ck[z], cmk = zs_cmk[z];
-    const float2 zero = make_float2(0.f, 0.f);
-    const float2 *ca = cv + (size_t)ib * n_cells;
-    const float2 *cb = hasb ? ca + n_cells : ca;
-    const float2 xa = ca[max(ck, 0)], xam = ca[max(cmk, 0)];  // branch-free loads
-    const float2 xb = cb[max(ck, 0)], xbm = cb[max(cmk, 0)];
-    const float2 ga = ck >= 0 ? xa : zero;
-    const float2 gam = cmk >= 0 ? xam : zero;
-    const float2 gb = (hasb && ck >= 0) ? xb : zero;
-    const float2 gbm = (hasb && cmk >= 0) ? xbm : zero;
-    const float sg = ((r + u) & 1) ? -0.5f : 0.5f;
+    // cell sums of images a and b; absent cells (and an absent image b) read
+    // zero through the buffer range check
+    const auto rca = buf_rsrc(cv + (size_t)(2 * pl) * n_cells, (uint32_t)n_cells * 8u);
+    const auto rcb = buf_rsrc(cv + (size_t)(2 * pl + 1) * n_cells, hasb ? (uint32_t)n_cells * 8u : 0u);
+    const uint32_t ok = ck >= 0 ? (uint32_t)ck * 8u : kNoLoad;
+    const uint32_t om = cmk >= 0 ? (uint32_t)cmk * 8u : kNoLoad;
+    const float2 ga = buf_load_f2(rca, ok), gam = buf_load_f2(rca, om);
+    const float2 gb = buf_load_f2(rcb, ok), gbm = buf_load_f2(rcb, om);
+    const float sg = ((r + u) & 1) ? -hw : hw;  // (-1)^(u+v) / (2W)
     buf[pp * S + pidx<PS>(u)] = zval(ga, gam, gb, gbm, sg);
     if (two) buf[(PBW + pp) * S + pidx<PS>((N - u) & (N - 1))] = zval(gam, ga, gbm, gb, sg);
     const float hax = ga.x + gam.x, hay = ga.y - gam.y;
     const float hbx = gb.x + gbm.x, hby = gb.y - gbm.y;
-    atomicAdd(&s_e[2 * pp + 0], ew * (hax * hax + hay * hay));
-    atomicAdd(&s_e[2 * pp + 1], ew * (hbx * hbx + hby * hby));
+    const float ea = ew * (hax * hax + hay * hay), eb = ew * (hbx * hbx + hby * hby);
+#pragma unroll
+    for (int q = 0; q < PBW; ++q) {
+      e_acc[2 * q] += q == pp ? ea : 0.f;
+      e_acc[2 * q + 1] += q == pp ? eb : 0.f;
+    }
+  }
+  // the energy terms: a wave sum per image, then one LDS atomic per wave
+#pragma unroll
+  for (int q = 0; q < 2 * PBW; ++q) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e_acc[q] += __shfl_xor(e_acc[q], o, 64);
+  }
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < 2 * PBW; ++q)
+      if (e_acc[q] != 0.f) atomicAdd(&s_e[q], e_acc[q]);
   }
   __syncthreads();
   if (tid < 2 * PBW && pb0 + tid / 2 < pbn)
@@ -406,7 +421,6 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
   const auto rla = buf_rsrc(list + ((size_t)(2 * pl) * CB + cb) * capb, (uint32_t)capb * 4u);
   const auto rlb = buf_rsrc(list + ((size_t)(2 * pl + 1) * CB + cb) * capb, (uint32_t)capb * 4u);
   float bva = -__builtin_inff(), bvb = -__builtin_inff();
-  int bia = 0x7fffffff, bib = 0x7fffffff;
   uint32_t ca = 0, cbn = 0;
   fft_rest_blocks<Sh, COLS, NT, S, false, true>(buf, tw, tid, [&](int f, int k0, int ks, auto &v) {
     constexpr int R = sizeof(v) / sizeof(v[0]);
@@ -414,24 +428,16 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
     // are then never used (no record is written for it and no select reads
     // its list region), and the loop stays free of branches.
     //
-    // The R outputs come in increasing row order, so within this butterfly a
-    // strict comparison keeps the lowest flat index among equal values; the
-    // butterfly's best then merges into the running best by (value, index).
-    float ma = -__builtin_inff(), mb = -__builtin_inff();
-    int ra = 0, rb = 0;
+    // Only the peak value is tracked here; its lowest index is found after
+    // the tile's maximum is known (below).  The outputs are already image
+    // pixels: 1/W is folded into Z.
     float aa[R], ab[R];
     uint64_t ba[R], bb[R];  // wave masks of bracket members, per output row
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const float pa = v[r].x * inv_w, pb = v[r].y * inv_w;
-      if (pa > ma) {
-        ma = pa;
-        ra = r;
-      }
-      if (pb > mb) {
-        mb = pb;
-        rb = r;
-      }
+      const float pa = v[r].x, pb = v[r].y;
+      bva = fmaxf(bva, pa);
+      bvb = fmaxf(bvb, pb);
       aa[r] = fabsf(pa);
       ab[r] = fabsf(pb);
       // wave-uniform count below the bracket; members by one unsigned compare
@@ -439,18 +445,6 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
       cbn += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(ab[r] < lo_b));
       ba[r] = __builtin_amdgcn_ballot_w64(__float_as_uint(aa[r]) - ulo_a < uwid_a);
       bb[r] = __builtin_amdgcn_ballot_w64(__float_as_uint(ab[r]) - ulo_b < uwid_b);
-    }
-    {
-      const int ia = (k0 + ra * ks) * N + x0 + f;
-      if (better(ma, ia, bva, bia)) {
-        bva = ma;
-        bia = ia;
-      }
-      const int ib = (k0 + rb * ks) * N + x0 + f;
-      if (better(mb, ib, bvb, bib)) {
-        bvb = mb;
-        bib = ib;
-      }
     }
     // Compact the members into the list regions: one LDS reservation per
     // wave and image; a member's slot is the reservation plus the members
@@ -500,43 +494,60 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
       }
     }
   });
+  // Tile peak: the maximum first (wave, then workgroup), then the lowest flat
+  // index holding it.  Only waves with a thread whose own maximum equals the
+  // tile's look for the index, re-running the last pass from LDS.
+  const float ta = bva, tb = bvb;  // this thread's maxima
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    const float ova = __shfl_xor(bva, o, 64);
-    const int oia = __shfl_xor(bia, o, 64);
-    if (better(ova, oia, bva, bia)) {
-      bva = ova;
-      bia = oia;
-    }
-    const float ovb = __shfl_xor(bvb, o, 64);
-    const int oib = __shfl_xor(bib, o, 64);
-    if (better(ovb, oib, bvb, bib)) {
-      bvb = ovb;
-      bib = oib;
-    }
+    bva = fmaxf(bva, __shfl_xor(bva, o, 64));
+    bvb = fmaxf(bvb, __shfl_xor(bvb, o, 64));
   }
   if (lane == 0) {
     w_v[0][wid] = bva;
-    w_i[0][wid] = bia;
-    w_c[0][wid] = ca;
     w_v[1][wid] = bvb;
-    w_i[1][wid] = bib;
+    w_c[0][wid] = ca;
     w_c[1][wid] = cbn;
   }
   __syncthreads();
+  float pka = w_v[0][0], pkb = w_v[1][0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) {
+    pka = fmaxf(pka, w_v[0][w]);
+    pkb = fmaxf(pkb, w_v[1][w]);
+  }
+  const bool mine_a = ta == pka, mine_b = tb == pkb;
+  int bia = 0x7fffffff, bib = 0x7fffffff;
+  if (__builtin_amdgcn_ballot_w64(mine_a || mine_b)) {
+    fft_last_again<Sh, COLS, NT, S, false, true>(buf, tw, tid, [&](int f, int k0, int ks, auto &v) {
+      constexpr int R = sizeof(v) / sizeof(v[0]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int idx = (k0 + r * ks) * N + x0 + f;
+        if (mine_a && v[r].x == pka) bia = min(bia, idx);
+        if (mine_b && v[r].y == pkb) bib = min(bib, idx);
+      }
+    });
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    bia = min(bia, __shfl_xor(bia, o, 64));
+    bib = min(bib, __shfl_xor(bib, o, 64));
+  }
+  if (lane == 0) {
+    w_i[0][wid] = bia;
+    w_i[1][wid] = bib;
+  }
+  __syncthreads();
   if (tid < 2 && (tid == 0 || hasb)) {
-    float v = w_v[tid][0];
     int i = w_i[tid][0];
     uint32_t c = w_c[tid][0];
     for (int w = 1; w < NW; ++w) {
-      if (better(w_v[tid][w], w_i[tid][w], v, i)) {
-        v = w_v[tid][w];
-        i = w_i[tid][w];
-      }
+      i = min(i, w_i[tid][w]);
       c += w_c[tid][w];
     }
     ColPart cp;
-    cp.maxv = v;
+    cp.maxv = tid == 0 ? pka : pkb;
     cp.maxi = i;
     cp.cnt_lo = c;
     cp.n = s_cnt[tid];
@@ -1035,8 +1046,8 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
   RF_TIMED(tm, RF_K_ROWS, s,
            (k_rows_pairs<N><<<(unsigned)(npb * p->n_rp), RowPairCfg<N>::NT, 0, s>>>(
                cv, p->n_cells, nimg_w, p0, pbn, p->d_rp_row, p->d_rp_sa, p->d_rp_sb, p->n_rp,
-               p->n_rows, p->d_zs_off, p->d_zs_u, p->d_zs_ck, p->d_zs_cmk, p->d_tw, M,
-               epart)));
+               p->n_rows, p->d_zs_off, p->d_zs_u, p->d_zs_ck, p->d_zs_cmk, half_inv_w(p),
+               p->d_tw, M, epart)));
   const float inv_w = 1.0f / (float)p->W;
   const int cgrid = (pbn * sh.cbp + 7) / 8 * 8;
   RF_TIMED(tm, RF_K_COLS, s,

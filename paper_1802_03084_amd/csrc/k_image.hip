@@ -21,7 +21,7 @@ using namespace rf;
 template <int N>
 __global__ __launch_bounds__(RowCfg<N>::NT) void k_rows_dense(
     const float2 *__restrict__ grid, int nimg, const int32_t *__restrict__ rows, int n_rows,
-    int row_blocks, const float2 *__restrict__ tw, float2 *__restrict__ M) {
+    int row_blocks, float hw, const float2 *__restrict__ tw, float2 *__restrict__ M) {
   constexpr int F = RowCfg<N>::F, NT = RowCfg<N>::NT, S = RowCfg<N>::STRIDE;
   constexpr int PS = RowFft<N>::PS;
   __shared__ float2 buf[F * S];
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(RowCfg<N>::NT) void k_rows_dense(
         b = Gb[(size_t)r * N + u];
         bm = Gb[(size_t)rm * N + um];
       }
-      z = zval(a, am, b, bm, ((r + u) & 1) ? -0.5f : 0.5f);
+      z = zval(a, am, b, bm, ((r + u) & 1) ? -hw : hw);
     }
     buf[f * S + pidx<PS>(u)] = z;
   }
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(RowCfg<N>::NT) void k_rows_dense(
 template <int N>
 __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_image(
     const float2 *__restrict__ M, int n_rows, int vmax, int nimg,
-    float inv_w, const float2 *__restrict__ tw, float *__restrict__ img) {
+    const float2 *__restrict__ tw, float *__restrict__ img) {
   constexpr int COLS = ColCfg<N>::COLS, NT = ColCfg<N>::NT, S = ColCfg<N>::STRIDE;
   constexpr int CB = N / COLS;
   __shared__ float2 buf[COLS * S];
@@ -78,8 +78,8 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_image(
       buf, tw, tid,
       [&](int f, int i) { return buf_load_f2(rm, (uint32_t)(band_slot_raw(i, N, vmax) * N + f) * 8u); },
       [&](int f, int y, float2 v) {
-        ia[(size_t)y * N + f] = v.x * inv_w;
-        if (hasb) ib[(size_t)y * N + f] = v.y * inv_w;
+        ia[(size_t)y * N + f] = v.x;  // 1/W is folded into Z
+        if (hasb) ib[(size_t)y * N + f] = v.y;
       });
 }
 
@@ -88,15 +88,14 @@ rf_status image_dense_n(const rf_plan *p, const float2 *grid, int nimg, float *i
                         hipStream_t s) {
   const int npairs = (nimg + 1) / 2;
   if (npairs == 0) return RF_OK;
-  const float inv_w = p->W > 0 ? 1.0f / (float)p->W : 0.0f;
   if (p->n_rows == 0 || p->W == 0) return launch_zero_f32(img, (size_t)nimg * N * N, s);
   const int rb = (p->n_rows + RowCfg<N>::F - 1) / RowCfg<N>::F;
   k_rows_dense<N><<<(unsigned)((size_t)rb * npairs), RowCfg<N>::NT, 0, s>>>(
-      grid, nimg, p->d_rows, p->n_rows, rb, p->d_tw, ws);
+      grid, nimg, p->d_rows, p->n_rows, rb, half_inv_w(p), p->d_tw, ws);
   RF_HIP_TRY(hipGetLastError());
   constexpr int CB = N / ColCfg<N>::COLS;
   k_cols_image<N><<<(unsigned)((size_t)CB * npairs), ColCfg<N>::NT, 0, s>>>(
-      ws, p->n_rows, p->vmax, nimg, inv_w, p->d_tw, img);
+      ws, p->n_rows, p->vmax, nimg, p->d_tw, img);
   RF_HIP_TRY(hipGetLastError());
   return RF_OK;
 }

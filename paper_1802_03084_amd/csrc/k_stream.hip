@@ -10,6 +10,13 @@
 //
 // Resampling (Figure 2's loop over sampling times) is a decimating boxcar mean
 // accumulated in float32 in increasing sample order.
+//
+// Mean subtraction (section 3.1: the mean visibility in time is subtracted on
+// timescales below the fringe rate, which removes constant sources) works in
+// place on the segment: a thread owns one (baseline, channel, polarisation)
+// value, sums it over the segment in float64 with U loads in flight, then
+// subtracts the mean from every integration; CF16 storage is rounded back to
+// nearest even.
 #include "rf_internal.h"
 
 #include <hip/hip_fp16.h>
@@ -73,7 +80,55 @@ __global__ __launch_bounds__(kThreads) void k_resample(const Ein *__restrict__ i
   }
 }
 
+__device__ __forceinline__ void store_c(float2 *p, size_t i, float2 v) { p[i] = v; }
+__device__ __forceinline__ void store_c(__half2 *p, size_t i, float2 v) {
+  p[i] = __float22half2_rn(v);
+}
+
+template <typename E>
+__global__ __launch_bounds__(kThreads) void k_mean_subtract(E *__restrict__ vis, int nint,
+                                                            int nelem) {
+  const int e = blockIdx.x * kThreads + threadIdx.x;
+  if (e >= nelem) return;
+  constexpr int U = 8;
+  double sr = 0.0, si = 0.0;
+  for (int t0 = 0; t0 < nint; t0 += U) {
+    float2 x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      x[u] = load_c(vis, (size_t)min(t0 + u, nint - 1) * nelem + e);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (t0 + u < nint) {
+        sr += (double)x[u].x;
+        si += (double)x[u].y;
+      }
+  }
+  const float2 m = make_float2((float)(sr / nint), (float)(si / nint));
+  for (int t0 = 0; t0 < nint; t0 += U) {
+    float2 x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      x[u] = load_c(vis, (size_t)min(t0 + u, nint - 1) * nelem + e);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (t0 + u < nint)
+        store_c(vis, (size_t)(t0 + u) * nelem + e, make_float2(x[u].x - m.x, x[u].y - m.y));
+  }
+}
+
 }  // namespace
+
+rf_status launch_mean_subtract(const rf_plan *p, void *vis, hipStream_t s) {
+  const int nelem = p->nbl * p->nchan * p->npol;  // complex values per integration
+  const dim3 grid((nelem + kThreads - 1) / kThreads);
+  if (p->vis_dtype == RF_CF32)
+    k_mean_subtract<float2><<<grid, kThreads, 0, s>>>((float2 *)vis, p->nint, nelem);
+  else
+    k_mean_subtract<__half2><<<grid, kThreads, 0, s>>>((__half2 *)vis, p->nint, nelem);
+  RF_HIP_TRY(hipGetLastError());
+  return RF_OK;
+}
 
 rf_status launch_dedisperse(const rf_plan *p, const int32_t *d_delay_row, const void *in,
                             void *out, hipStream_t s) {

@@ -394,6 +394,11 @@ rf_status rf_plan_query(const rf_plan *p, rf_plan_info *info) {
   return RF_OK;
 }
 
+rf_status rf_subtract_mean(const rf_plan *p, void *d_vis, void *stream) {
+  if (!p || !d_vis) return RF_EINVAL;
+  return launch_mean_subtract(p, d_vis, (hipStream_t)stream);
+}
+
 rf_status rf_plan_set_tuning(rf_plan *p, int32_t lanes, int32_t m_budget_mb) {
   if (!p) return RF_EINVAL;
   if (lanes < 1 || lanes > 4 || m_budget_mb < 16 || m_budget_mb > 4096) return RF_ERANGE;

@@ -66,6 +66,12 @@ struct rf_plan {
   std::vector<int32_t> h_cells;
 };
 
+// Factor of the paired Hermitian Z values: 1/2 from the Hermitian part and
+// the image normalisation 1/W (applied once per grid value instead of once per
+// pixel).  Every path that forms Z uses this value, so their images agree bit
+// for bit.
+inline float half_inv_w(const rf_plan *p) { return p->W > 0 ? 0.5f * (1.0f / (float)p->W) : 0.0f; }
+
 // Slot of grid row r in the stored band |v| <= vmax, or -1 outside it.  The
 // band is stored in row order -vmax .. vmax, so the slot is (r + vmax) mod N
 // and slots past 2 vmax are the rows outside the band: a column load at slot
@@ -117,6 +123,7 @@ rf_status launch_zero_f32(float *p, size_t nfloat, hipStream_t s);
 
 // whole segment: fused path (k_fused.hip) and the step chain (rf_segment.cpp)
 size_t segment_ws_bytes(const rf_plan *p);
+rf_status launch_mean_subtract(const rf_plan *p, void *vis, hipStream_t s);
 size_t steps_ws_bytes(const rf_plan *p);
 rf_status run_segment_steps(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
                             int32_t *ncand, rf_image_stats *stats, void *ws, size_t ws_bytes,

@@ -39,7 +39,7 @@ struct Request {
   const rf_plan *plan = nullptr;
   const void *h_vis = nullptr;
   size_t vis_bytes = 0, ws_bytes = 0, bytes = 0;
-  int32_t cap = 0;
+  int32_t cap = 0, flags = 0;
   Clock::time_point released, started, done_at;
   size_t off = 0;  // arena block
   std::vector<rf_candidate> cand;
@@ -125,6 +125,10 @@ rf_status serve_one(rf_server *sv, Request *r, hipStream_t s) {
   int32_t *d_ncand =
       (int32_t *)((char *)d_cand + aup(sizeof(rf_candidate) * (size_t)std::max(r->cap, 1)));
   RF_HIP_TRY(hipMemcpyAsync(d_vis, r->h_vis, r->vis_bytes, hipMemcpyHostToDevice, s));
+  if (r->flags & RF_SERVE_SUBTRACT_MEAN) {
+    const rf_status sm = launch_mean_subtract(r->plan, d_vis, s);
+    if (sm != RF_OK) return sm;
+  }
   const rf_status st = rf_search_segment(r->plan, d_vis, d_cand, r->cap, d_ncand, nullptr, d_ws,
                                          r->ws_bytes, s);
   if (st != RF_OK) return st;
@@ -213,13 +217,15 @@ rf_status rf_server_create(void *d_arena, size_t arena_bytes, int32_t nslots, rf
 }
 
 rf_status rf_server_submit(rf_server *sv, const rf_plan *p, const void *h_vis, int32_t cap,
-                           int64_t *ticket) {
+                           int32_t flags, int64_t *ticket) {
   if (!sv || !p || !h_vis || !ticket) return RF_EINVAL;
   if (cap < 0) return RF_ERANGE;
+  if (flags & ~RF_SERVE_SUBTRACT_MEAN) return RF_EINVAL;
   Request *r = new Request();
   r->plan = p;
   r->h_vis = h_vis;
   r->cap = cap;
+  r->flags = flags;
   request_layout(p, cap, &r->vis_bytes, &r->ws_bytes, &r->bytes);
   {
     std::lock_guard<std::mutex> lk(sv->m);

@@ -317,6 +317,30 @@ def check_noise_sigma(o):
         assert abs(np.mean(sig) / pred - 1) < 0.05, (w, np.mean(sig), pred)
 
 
+# ---------------------------------------------------------------- mean subtraction
+
+def check_subtract_mean(o):
+    """Closed forms of subtracting the segment's time mean (section 3.1): a
+    constant source vanishes; an impulse A at t0 in an empty segment leaves
+    A (1 - 1/T) at t0 and -A/T elsewhere; the output's time mean is zero;
+    adding a constant to every integration changes nothing."""
+    rng = np.random.default_rng(5)
+    T, B, C, P = 12, 3, 5, 2
+    const = rng.standard_normal((B, C, P)) + 1j * rng.standard_normal((B, C, P))
+    out = o.subtract_mean(np.broadcast_to(const, (T, B, C, P)))
+    assert np.max(np.abs(out)) < 1e-12, "a constant source must vanish"
+    imp = np.zeros((T, B, C, P), np.complex128)
+    imp[4, 1, 2, 0] = 3.0 - 2.0j
+    out = o.subtract_mean(imp)
+    assert abs(out[4, 1, 2, 0] - (3.0 - 2.0j) * (1 - 1 / T)) < 1e-12
+    assert abs(out[7, 1, 2, 0] + (3.0 - 2.0j) / T) < 1e-12
+    assert np.max(np.abs(out[:, 0])) < 1e-15, "other baselines untouched"
+    x = rng.standard_normal((T, B, C, P)) + 1j * rng.standard_normal((T, B, C, P))
+    y = o.subtract_mean(x)
+    assert np.max(np.abs(y.sum(axis=0))) < 1e-12
+    assert np.max(np.abs(o.subtract_mean(x + const[None]) - y)) < 1e-12
+
+
 # ---------------------------------------------------------------- layout
 
 def check_table1_layout():
@@ -333,5 +357,5 @@ ALL_CHECKS = [
     check_sweep_example, check_cells, check_dedisperse, check_resample, check_stokes,
     check_grid, check_image_dft, check_image_single_cell, check_image_point_source,
     check_image_parseval, check_image_offset_source, check_image_linear, check_stats,
-    check_noise_sigma,
+    check_noise_sigma, check_subtract_mean,
 ]

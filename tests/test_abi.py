@@ -133,7 +133,7 @@ def test_server_arguments_rejected_without_gpu():
     assert L.rf_server_create(ctypes.c_void_p(4096), 1 << 20, 17, ctypes.byref(out)) == -3
     assert L.rf_server_create(ctypes.c_void_p(4097), 1 << 20, 2, ctypes.byref(out)) == -1
     assert L.rf_server_create(ctypes.c_void_p(4096), 1 << 20, 2, None) == -1
-    assert L.rf_server_submit(None, None, None, 0, ctypes.byref(t)) == -1
+    assert L.rf_server_submit(None, None, None, 0, 0, ctypes.byref(t)) == -1
     assert L.rf_server_wait(None, 1, None, 0, ctypes.byref(k), None) == -1
     assert L.rf_server_destroy(None) == -1
 

@@ -129,7 +129,25 @@ def _cells_no_freq(uvw, freq, du, dv):               # frequency dropped from u
     return np.rint(u / du).astype(np.int32), np.rint(v / dv).astype(np.int32)
 
 
+def _mean_over_baselines(vis):                     # mean over the wrong axis
+    v = np.asarray(vis).astype(np.complex128)
+    return v - v.mean(axis=1, keepdims=True)
+
+
+def _mean_unbiased(vis):                           # divides by T - 1
+    v = np.asarray(vis).astype(np.complex128)
+    return v - v.sum(axis=0, keepdims=True) / (v.shape[0] - 1)
+
+
+def _mean_of_first(vis):                           # subtracts the first integration
+    v = np.asarray(vis).astype(np.complex128)
+    return v - v[:1]
+
+
 MUTANTS = {
+    "mean over baselines": dict(subtract_mean=_mean_over_baselines),
+    "mean unbiased": dict(subtract_mean=_mean_unbiased),
+    "mean of first": dict(subtract_mean=_mean_of_first),
     "delay 1/nu": dict(delay_table=_delay_inv_nu),
     "delay floor": dict(delay_table=_delay_floor),
     "delay ref at bottom": dict(delay_table=_delay_ref_low),
