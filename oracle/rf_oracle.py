@@ -25,6 +25,10 @@ Functions and the passages they follow:
   search        section 3.1 / Figure 2 (the whole loop)
   subtract_mean section 3.1 (mean visibility subtracted on timescales below
                 the fringe rate), 3.2 (segments of about that length)
+  mock_signal   section 3.3 (mock transients inserted into the data to
+                measure the search's efficiency), 2.1 footnote (their sweep)
+  inject        the same, applied to stored visibilities with the storage
+                rounding (one rounding per mock, mocks in order)
 
 Parity pins live in tests/test_oracle_*.py; every function above is pinned
 there against closed forms, brute force, library special cases or the values
@@ -298,3 +302,80 @@ def image_at(vis, plan, i, j, k):
     w = plan.widths[j]
     dd = dedisperse_window(vis, plan.delays[i], k * w, k * w + w)
     return make_image(resample(dd, w)[0], plan)
+
+
+def mock_signal(mock, t, b, c, freq_ghz, uvw_m, tint_s, kdm):
+    """Complex visibility of one mock transient at integration t, baseline b,
+    channel c (broadcastable int arrays); complex128.
+
+    A mock (section 3.3: mock sources inserted into calibrated data test the
+    search's efficiency) is a dispersed boxcar point source, given as a dict
+    with dm (pc cm^-3), t0 (arrival at the highest channel, in integrations
+    from the segment start, may be fractional), width (integrations, > 0),
+    l, m (direction cosines from the phase centre) and amp (flux in
+    visibility units, the same in every polarisation).  In channel c it
+    arrives later by the cold-plasma lag K DM (1/nu_c^2 - 1/nu_top^2)
+    seconds (section 2.1 footnote); integration t holds the part of
+    [start, start + width) that overlaps [t, t + 1), so the flux is
+    conserved.  A point source at (l, m) has visibility
+    amp exp(-2 pi i (u l + v m)) with u, v in wavelengths (the sign
+    convention the imaging inverts).  Every step is one float64 operation in
+    the order written:
+        lag   = (K * DM) * (1/(nu*nu) - 1/(nu_top*nu_top))
+        start = t0 + lag / t_int;  end = start + width
+        frac  = min(t + 1, end) - max(t, start), nothing where frac <= 0
+        u_l   = (u_m * (nu * 1e9)) / c;  v_l likewise
+        phase = -(2 pi * (u_l * l + v_l * m))
+        value = (amp * frac) * (cos(phase) + i sin(phase))
+    """
+    f = np.asarray(freq_ghz, dtype=np.float64)
+    uvw = np.asarray(uvw_m, dtype=np.float64)
+    t, b, c = np.broadcast_arrays(np.asarray(t), np.asarray(b), np.asarray(c))
+    nu = f[c]
+    nu_top = np.max(f)
+    lag = (kdm * mock["dm"]) * (1.0 / (nu * nu) - 1.0 / (nu_top * nu_top))
+    start = mock["t0"] + lag / tint_s
+    end = start + mock["width"]
+    tt = t.astype(np.float64)
+    frac = np.minimum(tt + 1.0, end) - np.maximum(tt, start)
+    frac = np.where(frac > 0.0, frac, 0.0)
+    f_hz = nu * 1e9
+    u_l = (uvw[b, 0] * f_hz) / C_LIGHT
+    v_l = (uvw[b, 1] * f_hz) / C_LIGHT
+    phase = -(2.0 * math.pi * (u_l * mock["l"] + v_l * mock["m"]))
+    s = mock["amp"] * frac
+    return s * np.cos(phase) + 1j * (s * np.sin(phase))
+
+
+def round_storage(z, storage):
+    """Round complex128 values to the visibility storage: complex64
+    ("cf32"), or float16 [..., 2] ("cf16"), each part rounded to nearest
+    even directly from float64."""
+    z = np.asarray(z)
+    if storage == "cf32":
+        return z.astype(np.complex64)
+    out = np.empty(z.shape + (2,), dtype=np.float16)
+    out[..., 0] = z.real.astype(np.float16)
+    out[..., 1] = z.imag.astype(np.float16)
+    return out
+
+
+def inject(vis, mocks, freq_ghz, uvw_m, tint_s, kdm, t_first=0):
+    """Add mock transients to stored visibilities (section 3.3).
+
+    vis: complex64 [T][nbl][nchan][npol] or float16 [T][nbl][nchan][npol][2],
+    integrations t_first .. t_first + T - 1 of the segment.  Mocks are added
+    one at a time in the given order; after each, every value is the stored
+    value plus the mock's signal, formed in float64 and rounded once to the
+    storage type.  Returns a new array of the same type.
+    """
+    storage = "cf32" if np.iscomplexobj(vis) else "cf16"
+    cur = np.array(vis, copy=True)
+    T, B, C = cur.shape[0], cur.shape[1], cur.shape[2]
+    t = (np.arange(T) + t_first)[:, None, None]
+    b = np.arange(B)[None, :, None]
+    c = np.arange(C)[None, None, :]
+    for mk in mocks:
+        sig = mock_signal(mk, t, b, c, freq_ghz, uvw_m, tint_s, kdm)[..., None]
+        cur = round_storage(as_complex(cur).astype(np.complex128) + sig, storage)
+    return cur

@@ -340,6 +340,185 @@ def check_subtract_mean(o):
     assert np.max(np.abs(y.sum(axis=0))) < 1e-12
     assert np.max(np.abs(o.subtract_mean(x + const[None]) - y)) < 1e-12
 
+# ---------------------------------------------------------------- mock injection
+
+def _mock(**kw):
+    m = dict(dm=0.0, t0=0.0, width=1.0, l=0.0, m=0.0, amp=1.0)
+    m.update(kw)
+    return m
+
+
+def _one_baseline(u_m=0.0, v_m=0.0):
+    return np.array([[u_m, v_m, 0.0]])
+
+
+def check_inject_boxcar(o):
+    """A DM 0 mock at the phase centre starting on an integration boundary
+    adds exactly amp to `width` whole integrations of every baseline,
+    channel and polarisation, and nothing elsewhere."""
+    T, B, C, P = 10, 3, 4, 2
+    uvw = np.array([[10.0, -3.0, 0.0], [0.0, 7.5, 0.0], [-120.0, 44.0, 0.0]])
+    f = centres(1.0, 2.0, C)
+    vis = np.zeros((T, B, C, P), np.complex64)
+    out = o.inject(vis, [_mock(t0=3.0, width=2.0, amp=0.5)], f, uvw, 0.005, 4.15e-3)
+    want = np.zeros((T, B, C, P), np.complex64)
+    want[3:5] = 0.5
+    assert out.dtype == np.complex64 and np.array_equal(out, want)
+
+
+def check_inject_fractional(o):
+    """Fractional start and width split the flux by overlap: [2.25, 3.75)
+    puts 3/4 of amp in integrations 2 and 3; [5.5, 8.0) puts 1/2, 1, 1."""
+    C = 2
+    f = centres(1.0, 2.0, C)
+    vis = np.zeros((10, 1, C, 1), np.complex64)
+    out = o.inject(vis, [_mock(t0=2.25, width=1.5, amp=2.0)], f, _one_baseline(), 0.01, 4.15e-3)
+    got = out[:, 0, 0, 0].real
+    want = np.zeros(10)
+    want[2] = want[3] = 1.5
+    assert np.array_equal(got, want), got
+    out = o.inject(vis, [_mock(t0=5.5, width=2.5, amp=1.0)], f, _one_baseline(), 0.01, 4.15e-3)
+    got = out[:, 0, 1, 0].real
+    want = np.zeros(10)
+    want[5], want[6], want[7] = 0.5, 1.0, 1.0
+    assert np.array_equal(got, want), got
+
+
+def check_inject_dispersion(o):
+    """The sweep follows the printed law (4.15 ms DM / nu^2, section 2.1
+    footnote), relative to the highest channel: channels at 1 GHz and 2 GHz,
+    DM 10, 1 ms integrations: the 1 GHz channel arrives 31.125 ms after the
+    2 GHz one, so a width-1 pulse at t0 = 4 lands in integrations 35 and 36
+    (7/8 and 1/8 of its flux) at 1 GHz and in integration 4 at 2 GHz."""
+    k = paper_values()["dispersion_law"]["delay_ms_per_dm_at_1ghz"] * 1e-3
+    f = np.array([1.0, 2.0])
+    vis = np.zeros((48, 1, 2, 1), np.complex64)
+    out = o.inject(vis, [_mock(dm=10.0, t0=4.0, width=1.0, amp=1.0)], f, _one_baseline(), 1e-3, k)
+    lo = out[:, 0, 0, 0].real.astype(np.float64)
+    hi = out[:, 0, 1, 0].real.astype(np.float64)
+    assert np.nonzero(hi)[0].tolist() == [4] and hi[4] == 1.0, hi
+    assert np.nonzero(lo)[0].tolist() == [35, 36], np.nonzero(lo)
+    assert abs(lo[35] - 0.875) < 1e-6 and abs(lo[36] - 0.125) < 1e-6, lo[35:37]
+
+
+def check_inject_phase(o):
+    """Visibility of a point source: amp exp(-2 pi i (u l + v m)), u and v in
+    wavelengths.  A baseline of c / 1 GHz metres east is one wavelength at
+    1 GHz: l = 1/4 gives -i amp, l = 1/8 gives amp (1 - i)/sqrt(2); a north
+    baseline with m = -1/4 gives +i amp."""
+    lam = 299792458.0 / 1e9
+    f = np.array([1.0])
+    vis = np.zeros((2, 1, 1, 2), np.complex64)
+    for uvw, l, m, want in [(_one_baseline(u_m=lam), 0.25, 0.0, -1j),
+                            (_one_baseline(u_m=lam), 0.125, 0.0, (1 - 1j) / math.sqrt(2)),
+                            (_one_baseline(v_m=lam), 0.0, -0.25, 1j),
+                            (_one_baseline(u_m=2 * lam, v_m=lam), 0.125, 0.25, -1.0)]:
+        out = o.inject(vis, [_mock(l=l, m=m, amp=3.0)], f, uvw, 0.005, 4.15e-3)
+        assert np.max(np.abs(out[0, 0, 0, :] - 3.0 * want)) < 1e-6, (l, m, out[0, 0, 0])
+        assert np.max(np.abs(out[1])) == 0.0
+
+
+def check_inject_flux(o):
+    """Flux conservation: a mock wholly inside the segment adds amp * width
+    times its phasor, summed over time, in every (baseline, channel); the
+    phasor has modulus amp regardless of frequency."""
+    rng = np.random.default_rng(11)
+    T, C = 64, 16
+    uvw = np.column_stack([rng.uniform(-800, 800, 5), rng.uniform(-800, 800, 5), np.zeros(5)])
+    f = centres(1.0, 2.0, C)
+    mk = _mock(dm=37.3, t0=6.3, width=3.7, l=0.004, m=-0.007, amp=1.0)
+    vis = np.zeros((T, 5, C, 1), np.complex128)
+    t = np.arange(T)[:, None, None]
+    sig = o.mock_signal(mk, t, np.arange(5)[None, :, None], np.arange(C)[None, None, :], f, uvw,
+                        0.005, 4.15e-3)
+    tot = sig.sum(axis=0)
+    assert np.max(np.abs(np.abs(tot) - 3.7)) < 1e-12, np.abs(tot)
+    # the sum over time is width times the single-integration phasor
+    one = o.mock_signal(dict(mk, dm=0.0, t0=0.0, width=1.0), np.zeros((1, 1, 1), int),
+                        np.arange(5)[None, :, None], np.arange(C)[None, None, :], f, uvw, 0.005, 4.15e-3)
+    assert np.max(np.abs(tot - 3.7 * one[0])) < 1e-12
+    del vis
+
+
+def check_inject_images_at_pixel(o):
+    """A mock placed at pixel (X0, Y0) (l = (X0 - N/2)/(N du), likewise m)
+    images at (X0, Y0) with a peak close to its amplitude: injection and
+    imaging follow one sign convention."""
+    from rfgen import synth
+    pos = synth.y_array_positions(27)
+    uvw = synth.baseline_uvw(pos)
+    f = centres(1.0, 2.0, 32)
+    N = 128
+    du = synth.default_cell_size(uvw, f, N)
+    iu, iv = o.cell_table(uvw, f, du, du)
+    valid = o.valid_cells(iu, iv, N)
+    W = int(np.count_nonzero(valid))
+    for X0, Y0 in [(N // 2 + 5, N // 2 - 3), (N // 2 - 7, N // 2 + 6)]:
+        l, m = (X0 - N / 2) / (N * du), (Y0 - N / 2) / (N * du)
+        vis = np.zeros((1, uvw.shape[0], 32, 2), np.complex64)
+        out = o.inject(vis, [_mock(l=l, m=m, amp=0.8)], f, uvw, 0.005, 4.15e-3)
+        img = o.image(o.grid(o.stokes_i(o.as_complex(out[0])), iu, iv, valid, N), W)
+        peak, x, y, _, _ = o.image_stats(img)
+        assert (x, y) == (X0, Y0), (x, y, X0, Y0)
+        assert 0.98 * 0.8 <= peak <= 0.8 * (1 + 1e-6), peak
+
+
+def _exact_round(x, mant_bits, emin):
+    """Round-to-nearest-even of the float x to a binary format with
+    mant_bits stored fraction bits and minimum normal exponent emin, by exact
+    rational arithmetic (brute force on the rounding definition)."""
+    from fractions import Fraction
+    if x == 0.0:
+        return 0.0
+    X = Fraction(abs(x))
+    e = 0
+    while Fraction(2) ** e > X:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= X:
+        e += 1
+    q = Fraction(2) ** (max(e, emin) - mant_bits)
+    n = X / q
+    fl = n.numerator // n.denominator
+    r = n - fl
+    if r > Fraction(1, 2) or (r == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    return math.copysign(float(fl * q), x)
+
+
+def check_inject_storage_rounding(o):
+    """A mock's float64 sum with the stored value is rounded once, to nearest
+    even, to the storage type: exact ties and values a hair off a tie go the
+    way the rounding definition says, for float16 and float32 storage."""
+    f = np.array([1.0])
+    for storage, mant, emin, old in [("cf16", 10, -14, 1.0), ("cf16", 10, -14, -0.3330078125),
+                                     ("cf32", 23, -126, 1.0), ("cf32", 23, -126, 0.1)]:
+        dt = np.float16 if storage == "cf16" else np.float32
+        ulp = float(np.spacing(dt(old)))
+        for d in (0.5 * ulp, 1.5 * ulp, 0.5 * ulp * (1 + 2.0 ** -30), 0.5 * ulp * (1 - 2.0 ** -30), 0.25 * ulp):
+            if storage == "cf16":
+                vis = np.zeros((1, 1, 1, 1, 2), np.float16)
+                vis[..., 0] = old
+                out = o.inject(vis, [_mock(amp=d)], f, _one_baseline(), 0.005, 4.15e-3)
+                got = float(out[0, 0, 0, 0, 0])
+                assert out.dtype == np.float16
+            else:
+                vis = np.full((1, 1, 1, 1), old, np.complex64)
+                out = o.inject(vis, [_mock(amp=d)], f, _one_baseline(), 0.005, 4.15e-3)
+                got = float(out[0, 0, 0, 0].real)
+            want = _exact_round(float(dt(old)) + d, mant, emin)
+            assert got == want, (storage, old, d, got, want)
+
+
+def check_inject_order(o):
+    """Two mocks are added one after the other, each rounded to the storage:
+    in float16, 1 + 2^-11 + 2^-11 is 1 (each addition is a tie to even),
+    not 1 + 2^-10."""
+    f = np.array([1.0])
+    vis = np.zeros((1, 1, 1, 1, 2), np.float16)
+    vis[..., 0] = 1.0
+    out = o.inject(vis, [_mock(amp=2.0 ** -11), _mock(amp=2.0 ** -11)], f, _one_baseline(), 0.005, 4.15e-3)
+    assert float(out[0, 0, 0, 0, 0]) == 1.0
+
 
 # ---------------------------------------------------------------- layout
 
@@ -357,5 +536,7 @@ ALL_CHECKS = [
     check_sweep_example, check_cells, check_dedisperse, check_resample, check_stokes,
     check_grid, check_image_dft, check_image_single_cell, check_image_point_source,
     check_image_parseval, check_image_offset_source, check_image_linear, check_stats,
-    check_noise_sigma, check_subtract_mean,
+    check_noise_sigma, check_subtract_mean, check_inject_boxcar, check_inject_fractional,
+    check_inject_dispersion, check_inject_phase, check_inject_flux, check_inject_images_at_pixel,
+    check_inject_storage_rounding, check_inject_order,
 ]

@@ -5,6 +5,7 @@ plausibly wrong version (a dropped term, a wrong sign, a swapped index, a
 transposed operand).  At least one pin must reject every mutant; otherwise the
 pins would not be evidence that the oracle is right.
 """
+import math
 import types
 
 import numpy as np
@@ -12,14 +13,25 @@ import pytest
 
 import oracle
 from oracle import rf_oracle as ro
+from oracle.rf_oracle import C_LIGHT
 import pins
 
 
 def mutant(**repl):
-    ns = types.SimpleNamespace(**{k: getattr(ro, k) for k in dir(ro) if not k.startswith("__")})
-    for k, v in repl.items():
-        setattr(ns, k, v)
-    return ns
+    """The oracle's namespace with some functions replaced.  Every oracle
+    function is rebound to globals holding the replacements, so a function
+    that calls a replaced one (inject -> mock_signal) sees the mistake too."""
+    g = dict(ro.__dict__)
+    g.update(repl)
+    ns = {}
+    for k, v in g.items():
+        if k.startswith("__"):
+            continue
+        if isinstance(v, types.FunctionType) and v.__module__ == ro.__name__ and k not in repl:
+            v = types.FunctionType(v.__code__, g, v.__name__, v.__defaults__, v.__closure__)
+            g[k] = v
+        ns[k] = v
+    return types.SimpleNamespace(**ns)
 
 
 def _delay_inv_nu(freq, dms, tint, kdm):             # 1/nu instead of 1/nu^2
@@ -144,6 +156,65 @@ def _mean_of_first(vis):                           # subtracts the first integra
     return v - v[:1]
 
 
+def _signal_with(**change):
+    """mock_signal with one planted change (keyword switches below)."""
+    def sig(mock, t, b, c, freq_ghz, uvw_m, tint_s, kdm):
+        f = np.asarray(freq_ghz, float)
+        uvw = np.asarray(uvw_m, float)
+        t, b, c = np.broadcast_arrays(np.asarray(t), np.asarray(b), np.asarray(c))
+        nu = f[c]
+        ref = f.min() if change.get("ref_low") else f.max()
+        power = 1 if change.get("inv_nu") else 2
+        lag = (kdm * mock["dm"]) * (1.0 / nu ** power - 1.0 / ref ** power)
+        if change.get("lag_sign"):
+            lag = -lag
+        start = mock["t0"] + lag / tint_s
+        width = 1.0 if change.get("no_width") else mock["width"]
+        end = start + width
+        tt = t.astype(float)
+        if change.get("no_split"):
+            frac = np.where(tt == np.floor(start), width, 0.0)
+        else:
+            frac = np.maximum(np.minimum(tt + 1.0, end) - np.maximum(tt, start), 0.0)
+        f_hz = nu * 1e9
+        u_l = (uvw[b, 0] * f_hz) / C_LIGHT
+        v_l = (uvw[b, 1] * f_hz) / C_LIGHT
+        l, m = (mock["m"], mock["l"]) if change.get("lm_swapped") else (mock["l"], mock["m"])
+        sign = 1.0 if change.get("phase_sign") else -1.0
+        phase = sign * (2.0 * math.pi * (u_l * l + v_l * m))
+        s = mock["amp"] * frac
+        return s * np.cos(phase) + 1j * (s * np.sin(phase))
+    return sig
+
+
+def _inject_first_pol(vis, mocks, freq, uvw, tint, kdm, t_first=0):  # only polarisation 0
+    out = ro.inject(vis, mocks, freq, uvw, tint, kdm, t_first)
+    out[:, :, :, 1:] = vis[:, :, :, 1:]
+    return out
+
+
+def _inject_once(vis, mocks, freq, uvw, tint, kdm, t_first=0):       # one rounding for all mocks
+    storage = "cf32" if np.iscomplexobj(vis) else "cf16"
+    T, B, C = vis.shape[:3]
+    t = (np.arange(T) + t_first)[:, None, None]
+    b = np.arange(B)[None, :, None]
+    c = np.arange(C)[None, None, :]
+    tot = ro.as_complex(vis).astype(complex)
+    for mk in mocks:
+        tot = tot + ro.mock_signal(mk, t, b, c, freq, uvw, tint, kdm)[..., None]
+    return ro.round_storage(tot, storage)
+
+
+def _round_via_f32(z, storage):                                      # float16 via float32
+    z = np.asarray(z)
+    if storage == "cf32":
+        return z.astype(np.complex64)
+    out = np.empty(z.shape + (2,), np.float16)
+    out[..., 0] = z.real.astype(np.float32).astype(np.float16)
+    out[..., 1] = z.imag.astype(np.float32).astype(np.float16)
+    return out
+
+
 MUTANTS = {
     "mean over baselines": dict(subtract_mean=_mean_over_baselines),
     "mean unbiased": dict(subtract_mean=_mean_unbiased),
@@ -167,6 +238,16 @@ MUTANTS = {
     "peak abs": dict(image_stats=_stats_absmax),
     "stats xy swapped": dict(image_stats=_stats_xy_swapped),
     "cells no freq": dict(cell_table=_cells_no_freq),
+    "mock phase sign": dict(mock_signal=_signal_with(phase_sign=True)),
+    "mock lag 1/nu": dict(mock_signal=_signal_with(inv_nu=True)),
+    "mock lag ref at bottom": dict(mock_signal=_signal_with(ref_low=True)),
+    "mock lag sign": dict(mock_signal=_signal_with(lag_sign=True)),
+    "mock width ignored": dict(mock_signal=_signal_with(no_width=True)),
+    "mock flux not split": dict(mock_signal=_signal_with(no_split=True)),
+    "mock l m swapped": dict(mock_signal=_signal_with(lm_swapped=True)),
+    "mock first pol only": dict(inject=_inject_first_pol),
+    "mock single rounding": dict(inject=_inject_once),
+    "mock f16 via f32": dict(round_storage=_round_via_f32),
 }
 
 
