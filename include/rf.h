@@ -344,6 +344,59 @@ rf_status rf_server_destroy(rf_server *server);
 rf_status rf_subtract_mean(const rf_plan *plan, void *d_vis, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Synthetic data: mock transients and counter-based noise.
+ * ------------------------------------------------------------------------ */
+
+/* A mock transient (section 3.3: mock sources are inserted into calibrated
+ * data to measure the search's efficiency and sensitivity): a dispersed
+ * boxcar point source.  48 bytes. */
+typedef struct rf_mock {
+  double dm;     /* pc cm^-3; sweep follows the plan's kdm (section 2.1 footnote) */
+  double t0;     /* arrival at the highest channel, integrations from the
+                    buffer's first integration (fractional allowed)            */
+  double width;  /* duration in integrations, > 0 (fractional allowed)        */
+  double l, m;   /* direction cosines from the phase centre                   */
+  double amp;    /* flux in visibility units, the same in every polarisation  */
+} rf_mock;
+
+/* Adds mocks[0..nmock) (host array, read before the call returns) to d_vis in
+ * place: the plan's segment layout and storage type, nint integrations that
+ * are integrations t_first .. t_first + nint - 1 of the segment the mocks'
+ * t0 refer to.  In channel c a mock occupies [s, s + width) integrations with
+ * s = t0 + ((kdm * dm) * (1/(nu_c*nu_c) - 1/(nu_top*nu_top))) / t_int;
+ * integration t receives amp * |[t, t+1) overlap| * exp(-2 pi i (u l + v m)),
+ * u and v the baseline in wavelengths at nu_c, in every polarisation.  Lag,
+ * overlap and phase are float64 operations in that order (no contraction),
+ * in absolute integrations, so a segment filled window by window gets the
+ * same values as one filled at once.  Each mock's sum with the stored value is
+ * rounded once to the storage type (nearest even), mocks in array order.
+ * Parts of a sweep outside the window are dropped.  With CF16 storage a
+ * per-sample signal of a few float16 spacings of the stored values is
+ * quantised against them without dither (a unit-noise segment loses about
+ * 0.4% of a 4e-3 signal): to model data whose signal was present before
+ * storage, inject into CF32 and round once.  Asynchronous on `stream`.
+ * RF_EINVAL on NULL or nmock < 0, RF_ERANGE for a non-finite field,
+ * width <= 0, |t0| > 1e15, |dm| > 1e9 or t_first outside [0, 2^50]. */
+rf_status rf_inject(const rf_plan *plan, const rf_mock *h_mocks, int32_t nmock, int64_t t_first,
+                    void *d_vis, void *stream);
+
+/* Fills d_vis (the plan's segment layout and storage, nint integrations) with
+ * complex Gaussian noise, Re and Im each N(0, 1), of integrations t_first ..
+ * t_first + nint - 1 of a stream: complex element e = ((t * nbl + b) * nchan
+ * + c) * npol + p (t absolute) takes Philox4x32-10 (Salmon et al. 2011)
+ * block e/2, counter (e/2 mod 2^32, e/2 div 2^32, stream, 0), key (seed mod
+ * 2^32, seed div 2^32); words (x0, x1) for even e, (x2, x3) for odd e give
+ * u = (x + 1/2) 2^-32 and the Box-Muller pair (Box and Muller 1958)
+ * sqrt(-2 ln u_a) (cos, sin)(2 pi u_b) in float64, rounded to float32 (CF16:
+ * those float32 values rounded to nearest even).  Every element depends only
+ * on (seed, stream, e), so overlapping windows hold the same values.  Not
+ * part of the search; a source of large synthetic segments on the device.
+ * Asynchronous on `stream`.  RF_EINVAL on NULL, RF_ERANGE if t_first < 0 or
+ * the last element index would pass 2^61. */
+rf_status rf_noise(const rf_plan *plan, uint64_t seed, uint32_t stream_id, int64_t t_first,
+                   void *d_vis, void *stream);
+
+/* ------------------------------------------------------------------------
  * Tuning and batches.
  * ------------------------------------------------------------------------ */
 

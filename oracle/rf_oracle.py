@@ -27,7 +27,7 @@ Functions and the passages they follow:
                 the fringe rate), 3.2 (segments of about that length)
   mock_signal   section 3.3 (mock transients inserted into the data to
                 measure the search's efficiency), 2.1 footnote (their sweep)
-  inject        the same, applied to stored visibilities with the storage
+  inject(_at)   the same, applied to stored visibilities with the storage
                 rounding (one rounding per mock, mocks in order)
 
 Parity pins live in tests/test_oracle_*.py; every function above is pinned
@@ -360,22 +360,30 @@ def round_storage(z, storage):
     return out
 
 
-def inject(vis, mocks, freq_ghz, uvw_m, tint_s, kdm, t_first=0):
-    """Add mock transients to stored visibilities (section 3.3).
+def inject_at(values, t, b, c, mocks, freq_ghz, uvw_m, tint_s, kdm):
+    """Stored values after adding mocks, at any set of positions.
 
-    vis: complex64 [T][nbl][nchan][npol] or float16 [T][nbl][nchan][npol][2],
-    integrations t_first .. t_first + T - 1 of the segment.  Mocks are added
-    one at a time in the given order; after each, every value is the stored
-    value plus the mock's signal, formed in float64 and rounded once to the
+    values: complex64 [..., npol] or float16 [..., npol, 2], the stored
+    visibilities at integration t, baseline b, channel c (int arrays
+    broadcastable to values' leading shape).  Mocks are added one at a time
+    in the given order; after each, every value is the stored value plus the
+    mock's signal (mock_signal), formed in float64 and rounded once to the
     storage type.  Returns a new array of the same type.
     """
-    storage = "cf32" if np.iscomplexobj(vis) else "cf16"
-    cur = np.array(vis, copy=True)
-    T, B, C = cur.shape[0], cur.shape[1], cur.shape[2]
-    t = (np.arange(T) + t_first)[:, None, None]
-    b = np.arange(B)[None, :, None]
-    c = np.arange(C)[None, None, :]
+    storage = "cf32" if np.iscomplexobj(values) else "cf16"
+    cur = np.array(values, copy=True)
     for mk in mocks:
         sig = mock_signal(mk, t, b, c, freq_ghz, uvw_m, tint_s, kdm)[..., None]
         cur = round_storage(as_complex(cur).astype(np.complex128) + sig, storage)
     return cur
+
+
+def inject(vis, mocks, freq_ghz, uvw_m, tint_s, kdm, t_first=0):
+    """Add mock transients to a stored segment (section 3.3): vis is complex64
+    [T][nbl][nchan][npol] or float16 [T][nbl][nchan][npol][2], integrations
+    t_first .. t_first + T - 1; see inject_at."""
+    T, B, C = vis.shape[0], vis.shape[1], vis.shape[2]
+    t = (np.arange(T) + t_first)[:, None, None]
+    b = np.arange(B)[None, :, None]
+    c = np.arange(C)[None, None, :]
+    return inject_at(vis, t, b, c, mocks, freq_ghz, uvw_m, tint_s, kdm)

@@ -120,12 +120,46 @@ class Plan:
     def handle(self):
         return self._h
 
+    freq_ghz = property(lambda self: self._freq)
+    uvw_m = property(lambda self: self._uvw)
+    dms = property(lambda self: self._dm)
+    tint_s = property(lambda self: self._args["tint_s"])
+    du = property(lambda self: self._args["du"])
+    dv = property(lambda self: self._args["dv"])
+    kdm = property(lambda self: self._args["kdm"])
+    threshold = property(lambda self: self._args["threshold"])
+
     def subtract_mean(self, vis, stream=None):
         """rf_subtract_mean: in place, each (baseline, channel, polarisation)
         value loses its mean over the segment."""
         self._check_vis(vis, self.nint)
         _lib.check(_lib.load().rf_subtract_mean(self._h, _ptr(vis), _stream(stream)),
                    "rf_subtract_mean")
+        return vis
+
+    def inject(self, vis, mocks, t_first=0, stream=None):
+        """rf_inject: adds mock transients to vis in place (mocks: dicts or
+        objects with dm, t0, width, l, m, amp; added in order); vis holds
+        integrations t_first .. t_first + nint - 1 of the mocks' segment."""
+        self._check_vis(vis, self.nint)
+        arr = (_lib.Mock * max(1, len(mocks)))()
+        for k, mk in enumerate(mocks):
+            get = mk.get if isinstance(mk, dict) else (lambda f, _m=mk: getattr(_m, f))
+            for f, _ in _lib.Mock._fields_:
+                setattr(arr[k], f, float(get(f)))
+        _lib.check(_lib.load().rf_inject(self._h, ctypes.cast(arr, ctypes.c_void_p), len(mocks),
+                                         int(t_first), _ptr(vis), _stream(stream)), "rf_inject")
+        return vis
+
+    def noise(self, vis=None, seed=0, stream_id=0, t_first=0, stream=None):
+        """rf_noise: fills vis (allocated if None) with the counter-based
+        complex Gaussian noise of integrations t_first .. t_first + nint - 1
+        of stream (seed, stream_id)."""
+        if vis is None:
+            vis = self.empty_vis()
+        self._check_vis(vis, self.nint)
+        _lib.check(_lib.load().rf_noise(self._h, int(seed) & ((1 << 64) - 1), int(stream_id),
+                                        int(t_first), _ptr(vis), _stream(stream)), "rf_noise")
         return vis
 
     def set_tuning(self, lanes, m_budget_mb):

@@ -78,6 +78,12 @@ class ServeTimes(ctypes.Structure):
     _fields_ = [("released_s", ctypes.c_double), ("started_s", ctypes.c_double),
                 ("done_s", ctypes.c_double), ("latency_s", ctypes.c_double)]
 
+class Mock(ctypes.Structure):
+    _fields_ = [("dm", ctypes.c_double), ("t0", ctypes.c_double), ("width", ctypes.c_double),
+                ("l", ctypes.c_double), ("m", ctypes.c_double), ("amp", ctypes.c_double)]
+
+
+assert ctypes.sizeof(Mock) == 48
 assert ctypes.sizeof(Candidate) == 32
 assert ctypes.sizeof(ImageStats) == 20
 assert ctypes.sizeof(ImageTag) == 12
@@ -109,6 +115,8 @@ SIGNATURES = {
     "rf_server_destroy": (c_i32, [c_vp]),
     "rf_plan_set_tuning": (c_i32, [c_vp, c_i32, c_i32]),
     "rf_subtract_mean": (c_i32, [c_vp, c_vp, c_vp]),
+    "rf_inject": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_vp, c_vp]),
+    "rf_noise": (c_i32, [c_vp, ctypes.c_uint64, ctypes.c_uint32, c_i64, c_vp, c_vp]),
     "rf_batch_workspace_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_size)]),
     "rf_batch_create": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp,
                                 ctypes.POINTER(c_vp)]),

@@ -172,6 +172,8 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
   p->d_zs_ck = (int32_t *)(base + L.zs_ck);
   p->d_zs_cmk = (int32_t *)(base + L.zs_cmk);
   p->d_cblk = (int32_t *)(base + L.cblk);
+  p->d_freq = d_freq;
+  p->d_uvw = d_uvw;
 
   RF_HIP_TRY(hipMemcpyAsync(d_freq, p->freq.data(), sizeof(double) * d->nchan,
                             hipMemcpyHostToDevice, s));
@@ -397,6 +399,28 @@ rf_status rf_plan_query(const rf_plan *p, rf_plan_info *info) {
 rf_status rf_subtract_mean(const rf_plan *p, void *d_vis, void *stream) {
   if (!p || !d_vis) return RF_EINVAL;
   return launch_mean_subtract(p, d_vis, (hipStream_t)stream);
+}
+
+rf_status rf_noise(const rf_plan *p, uint64_t seed, uint32_t stream, int64_t t_first, void *d_vis,
+                   void *stream_) {
+  if (!p || !d_vis) return RF_EINVAL;
+  const int64_t per = (int64_t)p->nbl * p->nchan * p->npol;
+  if (t_first < 0 || (per > 0 && t_first > (INT64_MAX / 4) / per - p->nint)) return RF_ERANGE;
+  return launch_noise(p, seed, stream, t_first, d_vis, (hipStream_t)stream_);
+}
+
+rf_status rf_inject(const rf_plan *p, const rf_mock *h_mocks, int32_t nmock, int64_t t_first,
+                    void *d_vis, void *stream) {
+  if (!p || !d_vis || nmock < 0 || (nmock > 0 && !h_mocks)) return RF_EINVAL;
+  if (t_first < 0 || t_first > ((int64_t)1 << 50)) return RF_ERANGE;
+  for (int k = 0; k < nmock; ++k) {
+    const rf_mock &m = h_mocks[k];
+    const double v[6] = {m.dm, m.t0, m.width, m.l, m.m, m.amp};
+    for (double x : v)
+      if (!std::isfinite(x)) return RF_ERANGE;
+    if (!(m.width > 0.0) || std::fabs(m.t0) > 1e15 || std::fabs(m.dm) > 1e9) return RF_ERANGE;
+  }
+  return launch_inject(p, h_mocks, nmock, t_first, d_vis, (hipStream_t)stream);
 }
 
 rf_status rf_plan_set_tuning(rf_plan *p, int32_t lanes, int32_t m_budget_mb) {

@@ -53,6 +53,8 @@ struct rf_plan {
   // at most 1024 contributors (a single heavier cell forms its own block)
   int32_t n_cblk;
   int32_t *d_cblk;          // [n_cblk + 1]
+  double *d_freq;           // [nchan] channel centres, GHz
+  double *d_uvw;            // [nbl][3] baseline vectors, metres
   int32_t *d_rp_row;        // [n_rp]
   int32_t *d_rp_sa;         // [n_rp]
   int32_t *d_rp_sb;         // [n_rp]
@@ -124,6 +126,7 @@ rf_status launch_zero_f32(float *p, size_t nfloat, hipStream_t s);
 // whole segment: fused path (k_fused.hip) and the step chain (rf_segment.cpp)
 size_t segment_ws_bytes(const rf_plan *p);
 rf_status launch_mean_subtract(const rf_plan *p, void *vis, hipStream_t s);
+
 size_t steps_ws_bytes(const rf_plan *p);
 rf_status run_segment_steps(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
                             int32_t *ncand, rf_image_stats *stats, void *ws, size_t ws_bytes,
@@ -138,3 +141,10 @@ rf_status batch_create(const rf_plan *const *plans, int nseg, const void *const 
                        rf_batch **out);
 rf_status batch_run(rf_batch *b, hipStream_t s);
 void batch_destroy(rf_batch *b);
+
+// synthetic data (k_mock.hip): counter-based noise and mock transients
+constexpr int kMocksPerLaunch = 64;  // mocks passed by value per injection launch
+rf_status launch_noise(const rf_plan *p, uint64_t seed, uint32_t stream, int64_t t_first,
+                       void *vis, hipStream_t s);
+rf_status launch_inject(const rf_plan *p, const rf_mock *mocks, int nmock, int64_t t_first,
+                        void *vis, hipStream_t s);

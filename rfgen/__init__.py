@@ -19,4 +19,5 @@ from .synth import (  # noqa: F401
     to_cf16,
     from_cf16,
 )
-from .presets import Preset, Pulse, tiny, survey, smallcase, serving, preset_by_name  # noqa: F401
+from .presets import Preset, Pulse, tiny, survey, large, smallcase, serving, preset_by_name  # noqa: F401
+from . import philox  # noqa: F401

@@ -74,6 +74,18 @@ class Preset:
         w = self.widths[p.width_idx]
         return p.snr / np.sqrt(2.0 * w * self.nbl * self.nchan)
 
+    def mocks(self):
+        """The pulses as mock-transient parameters (dm, t0, width, l, m, amp)
+        for device-side injection into device-generated noise."""
+        du, dv = self.cell()
+        out = []
+        for p in self.pulses:
+            l, m = synth.pixel_to_lm(p.x, p.y, self.npix, du, dv)
+            out.append(dict(dm=float(self.dms[p.dm_idx]), t0=float(p.t0),
+                            width=float(self.widths[p.width_idx]), l=l, m=m,
+                            amp=float(self.pulse_amp(p))))
+        return out
+
     def make_vis(self, with_pulses=True):
         vis = synth.noise_vis(self.seed, self.nint, self.nbl, self.nchan, self.npol)
         if with_pulses:
@@ -113,6 +125,25 @@ def survey():
                   widths=[1, 2, 4, 8], npix=1024, seed=1, pulses=pulses)
 
 
+def large():
+    """351 baselines, 8192 x 1 ms, 1024 channels over 2-4 GHz, 2 pols, DM
+    0-3000 in 400 trials, widths {1,2,4,8,16,32}, 2048^2 images; five S/N 20
+    pulses at DM 150-2560.  47 GB as complex64: its noise is generated on the
+    device (rfgen.philox defines the same values on the host, seed 4)."""
+    n = 2048
+    c = n // 2
+    pulses = [
+        Pulse(dm_idx=20, width_idx=0, t0=100, x=c + 60, y=c - 45),
+        Pulse(dm_idx=100, width_idx=2, t0=1200, x=c - 80, y=c + 33),
+        Pulse(dm_idx=180, width_idx=5, t0=2400, x=c + 17, y=c + 101),
+        Pulse(dm_idx=260, width_idx=3, t0=3800, x=c - 120, y=c - 7),
+        Pulse(dm_idx=340, width_idx=1, t0=5400, x=c + 9, y=c + 64),
+    ]
+    return Preset(name="large", nant=27, nint=8192, tint_s=0.001, f_lo_ghz=2.0,
+                  f_hi_ghz=4.0, nchan=1024, npol=2, dms=np.linspace(0, 3000, 400),
+                  widths=[1, 2, 4, 8, 16, 32], npix=n, seed=4, pulses=pulses)
+
+
 def smallcase(nant=10, nint=37, nchan=48, npix=128, seed=5, npol=2):
     """A small ragged shape for parity tests: sizes that are not multiples of
     the kernels' tiles, three DMs, widths {1,2,4}, one pulse."""
@@ -146,4 +177,4 @@ def serving(sub="C", seed=None):
 def preset_by_name(name):
     if name.startswith("serving-"):
         return serving(name.split("-", 1)[1])
-    return {"tiny": tiny, "survey": survey, "small": smallcase}[name]()
+    return {"tiny": tiny, "survey": survey, "small": smallcase, "large": large}[name]()

@@ -149,3 +149,11 @@ def test_tuning_and_batch_arguments_rejected_without_gpu():
     assert out.value is None
     assert L.rf_batch_run(None, None) == -1
     assert L.rf_batch_destroy(None) == -1
+
+
+def test_mock_and_noise_arguments_rejected_without_gpu():
+    from paper_1802_03084_amd import _lib
+    L = lib()
+    mk = (_lib.Mock * 1)()
+    assert L.rf_inject(None, mk, 1, 0, ctypes.c_void_p(4096), None) == -1
+    assert L.rf_noise(None, 1, 0, 0, ctypes.c_void_p(4096), None) == -1

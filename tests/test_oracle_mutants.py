@@ -193,13 +193,9 @@ def _inject_first_pol(vis, mocks, freq, uvw, tint, kdm, t_first=0):  # only pola
     return out
 
 
-def _inject_once(vis, mocks, freq, uvw, tint, kdm, t_first=0):       # one rounding for all mocks
-    storage = "cf32" if np.iscomplexobj(vis) else "cf16"
-    T, B, C = vis.shape[:3]
-    t = (np.arange(T) + t_first)[:, None, None]
-    b = np.arange(B)[None, :, None]
-    c = np.arange(C)[None, None, :]
-    tot = ro.as_complex(vis).astype(complex)
+def _inject_once(values, t, b, c, mocks, freq, uvw, tint, kdm):   # one rounding for all mocks
+    storage = "cf32" if np.iscomplexobj(values) else "cf16"
+    tot = ro.as_complex(values).astype(complex)
     for mk in mocks:
         tot = tot + ro.mock_signal(mk, t, b, c, freq, uvw, tint, kdm)[..., None]
     return ro.round_storage(tot, storage)
@@ -246,7 +242,7 @@ MUTANTS = {
     "mock flux not split": dict(mock_signal=_signal_with(no_split=True)),
     "mock l m swapped": dict(mock_signal=_signal_with(lm_swapped=True)),
     "mock first pol only": dict(inject=_inject_first_pol),
-    "mock single rounding": dict(inject=_inject_once),
+    "mock single rounding": dict(inject_at=_inject_once),
     "mock f16 via f32": dict(round_storage=_round_via_f32),
 }
 
