@@ -29,6 +29,10 @@ Functions and the passages they follow:
                 measure the search's efficiency), 2.1 footnote (their sweep)
   inject(_at)   the same, applied to stored visibilities with the storage
                 rounding (one rounding per mock, mocks in order)
+  candidate_cutout, candidate_spectrum
+                section 3.1 (a second, higher threshold, ~7 sigma, selects
+                candidates for visualisation), 3.3 (the candidate's image
+                and spectrum)
 
 Parity pins live in tests/test_oracle_*.py; every function above is pinned
 there against closed forms, brute force, library special cases or the values
@@ -387,3 +391,52 @@ def inject(vis, mocks, freq_ghz, uvw_m, tint_s, kdm, t_first=0):
     b = np.arange(B)[None, :, None]
     c = np.arange(C)[None, None, :]
     return inject_at(vis, t, b, c, mocks, freq_ghz, uvw_m, tint_s, kdm)
+
+
+def candidate_cutout(img, x, y, half):
+    """Second-tier product (section 3.1: candidates above a higher threshold,
+    typically 7 sigma, get visualisations; section 3.3: the candidate's image
+    and spectrum): the 2 half x 2 half window of the candidate's image whose
+    pixel (half, half) is the candidate pixel (x, y); the image is periodic
+    (an inverse DFT), so the window wraps at the edges.
+        out[r][q] = img[(y - half + r) mod N][(x - half + q) mod N]
+    """
+    N = img.shape[0]
+    rows = np.mod(y - half + np.arange(2 * half), N)
+    cols = np.mod(x - half + np.arange(2 * half), N)
+    return img[np.ix_(rows, cols)]
+
+
+def candidate_spectrum(vis, plan, i, j, k, x, y, nspec):
+    """Second-tier product: the dedispersed dynamic spectrum toward the
+    candidate pixel (x, y), float64 [nspec][nchan].
+
+    Row s is resampled integration kk = k - nspec // 2 + s of DM trial i and
+    width index j (zero when kk is outside [0, T // w)); column c is the mean
+    over the channel's gridded baselines of the Stokes I sample turned to the
+    pixel with the gridding's own cell phases:
+        spec[s][c] = (1/n_c) sum_{b: (b,c) gridded}
+                     Re( V_I[kk][b][c] exp(+2 pi i (iu (x - N/2) + iv (y - N/2)) / N) )
+    (0 for a channel with no gridded baseline).  So sum_c n_c spec[s][c] / W
+    is the image of (i, j, kk) at (x, y): the spectrum splits that pixel by
+    channel.
+    """
+    w = plan.widths[j]
+    T = vis.shape[0]
+    K = T // w
+    N = plan.npix
+    dX, dY = x - N // 2, y - N // 2
+    phase = np.exp(2j * np.pi * ((plan.iu * dX + plan.iv * dY) % N) / N)
+    valid = plan.valid
+    n_c = valid.sum(axis=0)
+    out = np.zeros((nspec, plan.iu.shape[1]), dtype=np.float64)
+    for s in range(nspec):
+        kk = k - nspec // 2 + s
+        if not 0 <= kk < K:
+            continue
+        dd = dedisperse_window(vis, plan.delays[i], kk * w, kk * w + w)
+        vi = stokes_i(resample(dd, w)[0])
+        turned = np.where(valid, (vi * phase).real, 0.0)
+        tot = turned.sum(axis=0)
+        out[s] = np.where(n_c > 0, tot / np.maximum(n_c, 1), 0.0)
+    return out

@@ -520,6 +520,84 @@ def check_inject_order(o):
     assert float(out[0, 0, 0, 0, 0]) == 1.0
 
 
+# ---------------------------------------------------------------- second-tier products
+
+def check_cutout(o):
+    """The cutout is the image rolled so the candidate pixel sits at (half,
+    half) (numpy.roll as the library special case), wrapping at every edge."""
+    rng = np.random.default_rng(2)
+    img = rng.standard_normal((32, 32))
+    for x, y, h in [(10, 20, 4), (0, 31, 5), (31, 0, 16), (16, 16, 1)]:
+        cut = o.candidate_cutout(img, x, y, h)
+        want = np.roll(img, (h - y, h - x), axis=(0, 1))[:2 * h, :2 * h]
+        assert cut.shape == (2 * h, 2 * h) and np.array_equal(cut, want), (x, y, h)
+        assert cut[h, h] == img[y, x]
+
+
+def _spectrum_case(o):
+    from rfgen import synth
+    uvw = synth.baseline_uvw(synth.y_array_positions(10))
+    f = centres(1.0, 2.0, 12)
+    N = 64
+    du = 0.6 * synth.default_cell_size(uvw, f, N)   # some pairs fall off the grid
+    plan = o.Plan(f, uvw, 0.005, np.array([0.0, 40.0]), [1, 2], N, du, du, nint=20)
+    return plan, uvw, f, N, du
+
+
+def check_spectrum_splits_pixel(o):
+    """Weighted by the channel's gridded baselines and divided by W, a
+    spectrum row adds up to the candidate pixel of that row's image: the
+    spectrum splits the image pixel by channel."""
+    plan, uvw, f, N, du = _spectrum_case(o)
+    n_c = plan.valid.sum(axis=0)
+    assert n_c.min() < n_c.max() and n_c.min() < uvw.shape[0], "the case must drop some pairs"
+    rng = np.random.default_rng(8)
+    vis = rng.standard_normal((20, uvw.shape[0], 12, 2)) + 1j * rng.standard_normal((20, uvw.shape[0], 12, 2))
+    for i, j, k, x, y in [(1, 1, 4, 37, 25), (0, 0, 19, 3, 60), (1, 0, 0, 32, 32)]:
+        spec = o.candidate_spectrum(vis, plan, i, j, k, x, y, 5)
+        K = 20 // plan.widths[j]
+        for s in range(5):
+            kk = k - 2 + s
+            got = float((spec[s] * n_c).sum() / plan.W)
+            if 0 <= kk < K:
+                want = o.image_at(vis, plan, i, j, kk)[y, x]
+                assert abs(got - want) < 1e-12, (i, j, k, s, got, want)
+            else:
+                assert np.all(spec[s] == 0.0)
+
+
+def check_spectrum_point_source(o):
+    """A steady source at the phase centre (V = A everywhere) has the
+    spectrum A in every channel with a gridded baseline, in every row inside
+    the segment, toward pixel (N/2, N/2)."""
+    plan, uvw, f, N, du = _spectrum_case(o)
+    vis = np.full((20, uvw.shape[0], 12, 2), 0.7 - 0.2j)
+    spec = o.candidate_spectrum(vis, plan, 0, 1, 9, N // 2, N // 2, 4)
+    n_c = plan.valid.sum(axis=0)
+    assert np.max(np.abs(spec[:3][:, n_c > 0] - 0.7)) < 1e-12
+    assert np.all(spec[3] == 0.0), "row k + 1 = 10 is past the 10 width-2 integrations"
+
+
+def check_spectrum_pulse(o):
+    """A noise-free pulse from pixel (x0, y0) at DM 0 in integration 6: toward
+    that pixel its row holds nearly the full flux in every gridded channel
+    (nearest-cell phase error <= pi |dx| / N), every other row is zero; toward
+    the mirrored pixel the flux is not there."""
+    from rfgen import synth
+    plan, uvw, f, N, du = _spectrum_case(o)
+    x0, y0 = N // 2 + 3, N // 2 - 2
+    l, m = synth.pixel_to_lm(x0, y0, N, du, du)
+    vis = np.zeros((20, uvw.shape[0], 12, 2), np.complex128)
+    synth.add_pulse(vis, uvw, f, 0.005, 4.15e-3, 0.0, 6, 1, l, m, 0.5)
+    spec = o.candidate_spectrum(vis, plan, 0, 0, 6, x0, y0, 3)
+    n_c = plan.valid.sum(axis=0)
+    assert np.all(spec[0] == 0) and np.all(spec[2] == 0)
+    row = spec[1][n_c > 0]
+    assert np.all(row > 0.5 * 0.95) and np.all(row <= 0.5 + 1e-12), row
+    away = o.candidate_spectrum(vis, plan, 0, 0, 6, N - x0, N - y0, 3)[1][n_c > 0]
+    assert np.mean(away) < 0.5 * 0.5, away
+
+
 # ---------------------------------------------------------------- layout
 
 def check_table1_layout():
@@ -538,5 +616,6 @@ ALL_CHECKS = [
     check_image_parseval, check_image_offset_source, check_image_linear, check_stats,
     check_noise_sigma, check_subtract_mean, check_inject_boxcar, check_inject_fractional,
     check_inject_dispersion, check_inject_phase, check_inject_flux, check_inject_images_at_pixel,
-    check_inject_storage_rounding, check_inject_order,
+    check_inject_storage_rounding, check_inject_order, check_cutout, check_spectrum_splits_pixel,
+    check_spectrum_point_source, check_spectrum_pulse,
 ]

@@ -211,6 +211,36 @@ def _round_via_f32(z, storage):                                      # float16 v
     return out
 
 
+def _spectrum_with(conj=False, no_dd=False, per_nbl=False, shift=0):
+    def spec(vis, plan, i, j, k, x, y, nspec):
+        w = plan.widths[j]
+        T = vis.shape[0]
+        N = plan.npix
+        sign = -1.0 if conj else 1.0
+        phase = np.exp(sign * 2j * np.pi * ((plan.iu * (x - N // 2) + plan.iv * (y - N // 2)) % N) / N)
+        n_c = plan.valid.sum(axis=0)
+        den = np.full_like(n_c, plan.iu.shape[0]) if per_nbl else np.maximum(n_c, 1)
+        out = np.zeros((nspec, plan.iu.shape[1]))
+        for s_ in range(nspec):
+            kk = k - nspec // 2 + s_ + shift
+            if not 0 <= kk < T // w:
+                continue
+            d = np.zeros_like(plan.delays[i]) if no_dd else plan.delays[i]
+            dd = ro.dedisperse_window(vis, d, kk * w, kk * w + w)
+            vi = ro.stokes_i(ro.resample(dd, w)[0])
+            out[s_] = np.where(n_c > 0, np.where(plan.valid, (vi * phase).real, 0).sum(axis=0) / den, 0)
+        return out
+    return spec
+
+
+def _cutout_transposed(img, x, y, half):
+    return ro.candidate_cutout(img, x, y, half).T
+
+
+def _cutout_off_by_one(img, x, y, half):
+    return ro.candidate_cutout(img, x, y + 1, half)
+
+
 MUTANTS = {
     "mean over baselines": dict(subtract_mean=_mean_over_baselines),
     "mean unbiased": dict(subtract_mean=_mean_unbiased),
@@ -244,6 +274,12 @@ MUTANTS = {
     "mock first pol only": dict(inject=_inject_first_pol),
     "mock single rounding": dict(inject_at=_inject_once),
     "mock f16 via f32": dict(round_storage=_round_via_f32),
+    "spectrum phase conjugated": dict(candidate_spectrum=_spectrum_with(conj=True)),
+    "spectrum not dedispersed": dict(candidate_spectrum=_spectrum_with(no_dd=True)),
+    "spectrum over all baselines": dict(candidate_spectrum=_spectrum_with(per_nbl=True)),
+    "spectrum rows shifted": dict(candidate_spectrum=_spectrum_with(shift=1)),
+    "cutout transposed": dict(candidate_cutout=_cutout_transposed),
+    "cutout off by one": dict(candidate_cutout=_cutout_off_by_one),
 }
 
 
