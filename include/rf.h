@@ -397,6 +397,40 @@ rf_status rf_noise(const rf_plan *plan, uint64_t seed, uint32_t stream_id, int64
                    void *d_vis, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Second-tier candidate products (section 3.1: candidates above a second,
+ * higher threshold, typically 7 sigma, get visualisations; section 3.3: the
+ * candidate's image and spectrum).
+ * ------------------------------------------------------------------------ */
+
+/* Workspace of rf_candidate_products for nspec spectrum rows: the gathered
+ * rows (nspec x nbl x nchan x npol complex64), one grid, one image and the
+ * imaging scratch of one image.  RF_ERANGE unless 1 <= nspec <= 4096. */
+rf_status rf_products_workspace_bytes(const rf_plan *plan, int32_t nspec, size_t *bytes);
+
+/* For each of h_cand[0..ncand) (host rows as the search returns them; the
+ * caller picks the tier, e.g. snr > 7; read before the call returns), from
+ * the segment d_vis the search ran on:
+ *   d_cutout [ncand][2 half][2 half] float (nullable): the window of the
+ *     candidate's image (DM trial dm_idx, width width_idx, resampled
+ *     integration t_int / w) with the candidate pixel at (half, half),
+ *     wrapping at the image edges;
+ *   d_spec [ncand][nspec][nchan] float (nullable): the dedispersed dynamic
+ *     spectrum toward the candidate pixel: row s is resampled integration
+ *     t_int / w - nspec/2 + s (zero outside the segment), channel c the mean
+ *     over its gridded baselines of Re(V_I exp(+2 pi i (iu (x - N/2) +
+ *     iv (y - N/2)) / N)), zero for a channel with none.  Weighted by the
+ *     channel's gridded baselines and divided by W a row sums to that row's
+ *     image pixel.
+ * Asynchronous on `stream`; d_ws (rf_products_workspace_bytes) is reused
+ * candidate after candidate.  RF_EINVAL on NULL arguments or ncand < 0,
+ * RF_ERANGE for half outside [1, N/2], nspec outside [1, 4096] or a row that
+ * names no image of the plan (index, t_int not a multiple of the width, pixel
+ * outside the image), RF_EWORKSPACE if ws_bytes is too small. */
+rf_status rf_candidate_products(const rf_plan *plan, const void *d_vis, const rf_candidate *h_cand,
+                                int32_t ncand, int32_t half, int32_t nspec, float *d_cutout,
+                                float *d_spec, void *d_ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Tuning and batches.
  * ------------------------------------------------------------------------ */
 

@@ -24,7 +24,7 @@ from ._lib import (RF_CF16, RF_CF32, RF_OP_IMAGE, RF_OP_SEARCH, RF_OP_SEGMENT,  
                    RF_OP_SEGMENT_STEPS,
                    Candidate, ImageStats, ImageTag, RFError)
 
-__all__ = ["Plan", "Server", "Batch", "RFError", "RF_CF32", "RF_CF16", "load_library", "CAND_DTYPE",
+__all__ = ["Plan", "Server", "Batch", "RFError", "RF_CF32", "RF_CF16", "load_library", "CAND_DTYPE", "second_tier",
            "STATS_DTYPE"]
 
 CAND_DTYPE = np.dtype([("dm_idx", "<i4"), ("width_idx", "<i4"), ("t_int", "<i4"), ("x", "<i4"),
@@ -32,6 +32,13 @@ CAND_DTYPE = np.dtype([("dm_idx", "<i4"), ("width_idx", "<i4"), ("t_int", "<i4")
 STATS_DTYPE = np.dtype([("peak", "<f4"), ("sigma", "<f4"), ("snr", "<f4"), ("x", "<i4"),
                         ("y", "<i4")])
 TAG_DTYPE = np.dtype([("dm_idx", "<i4"), ("width_idx", "<i4"), ("t_int", "<i4")])
+
+
+def second_tier(rows, threshold=7.0):
+    """Candidates above the second, higher threshold (section 3.1: about 7
+    sigma), which get image cutouts and spectra."""
+    rows = np.asarray(rows)
+    return rows[rows["snr"] > threshold]
 
 
 def load_library():
@@ -161,6 +168,32 @@ class Plan:
         _lib.check(_lib.load().rf_noise(self._h, int(seed) & ((1 << 64) - 1), int(stream_id),
                                         int(t_first), _ptr(vis), _stream(stream)), "rf_noise")
         return vis
+
+    def products_workspace_bytes(self, nspec):
+        n = _lib.c_size(0)
+        _lib.check(_lib.load().rf_products_workspace_bytes(self._h, int(nspec), ctypes.byref(n)),
+                   "rf_products_workspace_bytes")
+        return n.value
+
+    def candidate_products(self, vis, rows, half=32, nspec=16, cutouts=True, spectra=True,
+                           ws=None, stream=None):
+        """rf_candidate_products for candidate rows (CAND_DTYPE, e.g. the
+        second tier second_tier(rows)): returns (cutouts [n][2 half][2 half],
+        spectra [n][nspec][nchan]) float32 device tensors (None when not
+        asked for)."""
+        torch = _torch()
+        self._check_vis(vis, self.nint)
+        rows = np.ascontiguousarray(rows, dtype=CAND_DTYPE)
+        n = len(rows)
+        cut = torch.empty((n, 2 * half, 2 * half), dtype=torch.float32, device=self.device) if cutouts else None
+        spec = torch.empty((n, nspec, self.nchan), dtype=torch.float32, device=self.device) if spectra else None
+        if ws is None:
+            ws = torch.empty(max(1, self.products_workspace_bytes(nspec)), dtype=torch.uint8,
+                             device=self.device)
+        _lib.check(_lib.load().rf_candidate_products(
+            self._h, _ptr(vis), rows.ctypes.data_as(ctypes.c_void_p), n, int(half), int(nspec),
+            _ptr(cut), _ptr(spec), _ptr(ws), ws.numel(), _stream(stream)), "rf_candidate_products")
+        return cut, spec
 
     def set_tuning(self, lanes, m_budget_mb):
         """rf_plan_set_tuning: lane streams and the row-transformed batch

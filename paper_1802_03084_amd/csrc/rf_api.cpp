@@ -423,6 +423,33 @@ rf_status rf_inject(const rf_plan *p, const rf_mock *h_mocks, int32_t nmock, int
   return launch_inject(p, h_mocks, nmock, t_first, d_vis, (hipStream_t)stream);
 }
 
+rf_status rf_products_workspace_bytes(const rf_plan *p, int32_t nspec, size_t *bytes) {
+  if (!p || !bytes) return RF_EINVAL;
+  if (nspec < 1 || nspec > 4096) return RF_ERANGE;
+  *bytes = products_ws_bytes(p, nspec);
+  return RF_OK;
+}
+
+rf_status rf_candidate_products(const rf_plan *p, const void *d_vis, const rf_candidate *h_cand,
+                                int32_t ncand, int32_t half, int32_t nspec, float *d_cutout,
+                                float *d_spec, void *d_ws, size_t ws_bytes, void *stream) {
+  if (!p || !d_vis || ncand < 0 || (ncand > 0 && !h_cand)) return RF_EINVAL;
+  if (nspec < 1 || nspec > 4096 || half < 1 || half > p->npix / 2) return RF_ERANGE;
+  for (int n = 0; n < ncand; ++n) {
+    const rf_candidate &c = h_cand[n];
+    if (c.dm_idx < 0 || c.dm_idx >= p->ndm || c.width_idx < 0 || c.width_idx >= p->nwidth)
+      return RF_ERANGE;
+    const int w = p->width[c.width_idx];
+    if (c.t_int < 0 || c.t_int % w != 0 || c.t_int / w >= p->nint / w) return RF_ERANGE;
+    if (c.x < 0 || c.x >= p->npix || c.y < 0 || c.y >= p->npix) return RF_ERANGE;
+  }
+  if (ncand == 0 || (!d_cutout && !d_spec)) return RF_OK;
+  if (!d_ws) return RF_EINVAL;
+  if (ws_bytes < products_ws_bytes(p, nspec)) return RF_EWORKSPACE;
+  return run_products(p, d_vis, h_cand, ncand, half, nspec, d_cutout, d_spec, d_ws,
+                      (hipStream_t)stream);
+}
+
 rf_status rf_plan_set_tuning(rf_plan *p, int32_t lanes, int32_t m_budget_mb) {
   if (!p) return RF_EINVAL;
   if (lanes < 1 || lanes > 4 || m_budget_mb < 16 || m_budget_mb > 4096) return RF_ERANGE;

@@ -148,3 +148,9 @@ rf_status launch_noise(const rf_plan *p, uint64_t seed, uint32_t stream, int64_t
                        void *vis, hipStream_t s);
 rf_status launch_inject(const rf_plan *p, const rf_mock *mocks, int nmock, int64_t t_first,
                         void *vis, hipStream_t s);
+
+// second-tier candidate products (k_products.hip)
+size_t products_ws_bytes(const rf_plan *p, int nspec);
+rf_status run_products(const rf_plan *p, const void *vis, const rf_candidate *cand, int ncand,
+                       int half, int nspec, float *cutout, float *spec, void *ws,
+                       hipStream_t s);

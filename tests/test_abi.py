@@ -157,3 +157,10 @@ def test_mock_and_noise_arguments_rejected_without_gpu():
     mk = (_lib.Mock * 1)()
     assert L.rf_inject(None, mk, 1, 0, ctypes.c_void_p(4096), None) == -1
     assert L.rf_noise(None, 1, 0, 0, ctypes.c_void_p(4096), None) == -1
+
+
+def test_products_arguments_rejected_without_gpu():
+    L = lib()
+    n = ctypes.c_size_t(0)
+    assert L.rf_products_workspace_bytes(None, 16, ctypes.byref(n)) == -1
+    assert L.rf_candidate_products(None, None, None, 0, 8, 16, None, None, None, 0, None) == -1
