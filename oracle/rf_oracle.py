@@ -29,6 +29,10 @@ Functions and the passages they follow:
                 measure the search's efficiency), 2.1 footnote (their sweep)
   inject(_at)   the same, applied to stored visibilities with the storage
                 rounding (one rounding per mock, mocks in order)
+  time_spectrum, complex_image, amplitude_stats, periodic_search
+                section 3.1 footnote (a segment transformed to frequencies
+                along time, each frequency imaged), Figure 2 caption (a
+                modification of the innermost loop)
   candidate_cutout, candidate_spectrum
                 section 3.1 (a second, higher threshold, ~7 sigma, selects
                 candidates for visualisation), 3.3 (the candidate's image
@@ -440,3 +444,81 @@ def candidate_spectrum(vis, plan, i, j, k, x, y, nspec):
         tot = turned.sum(axis=0)
         out[s] = np.where(n_c > 0, tot / np.maximum(n_c, 1), 0.0)
     return out
+
+
+# Median of the amplitude of a complex Gaussian with unit variance per
+# quadrature (a Rayleigh variable of scale 1): sqrt(2 ln 2).
+RAYLEIGH_MEDIAN = math.sqrt(2.0 * math.log(2.0))
+
+
+def time_spectrum(vi):
+    """Fluctuation spectrum of a segment along time (section 3.1 footnote:
+    a time segment is Fourier transformed to frequencies): complex
+    [T][...] -> F[f] = (1/T) sum_t vi[t] exp(-2 pi i f t / T).  A steady
+    source of flux A gives F[0] = A; numpy's FFT is the library step."""
+    T = vi.shape[0]
+    return np.fft.fft(np.asarray(vi, dtype=np.complex128), axis=0) / T
+
+
+def complex_image(G, W):
+    """The image of a grid without taking the real part: (1/W) times the
+    shifted unnormalised inverse DFT (the same sum as `image`).  A fluctuation
+    frequency's grid has no Hermitian symmetry, so its sky is complex."""
+    N = G.shape[0]
+    return np.fft.fftshift(np.fft.ifft2(G) * (N * N)) / W
+
+
+def amplitude_stats(A):
+    """(peak, X, Y, sigma, snr) of an amplitude image A = |complex image|.
+
+    Readings (parity unpinned: the paper states the periodicity search in one
+    sentence): the statistic is the amplitude, whose peak is the fluctuation
+    amplitude of a point source; sigma is the noise per quadrature, estimated
+    as the lower median of A over sqrt(2 ln 2) (the median of the amplitude
+    of a complex Gaussian); snr = peak / sigma (0 when sigma == 0).  Ties go
+    to the lowest Y*N + X as in image_stats."""
+    N = A.shape[1]
+    flat = A.ravel()
+    idx = int(np.argmax(flat))
+    peak = float(flat[idx])
+    k = (flat.size - 1) // 2
+    med = float(np.partition(flat, k)[k])
+    sigma = med / RAYLEIGH_MEDIAN
+    snr = peak / sigma if sigma != 0.0 else 0.0
+    return peak, idx % N, idx // N, sigma, snr
+
+
+def periodic_search(vis, plan, select=None, keep_images=False):
+    """Periodicity search (section 3.1 footnote; Figure 2 caption: a
+    modification of the innermost loop).  For each DM trial: dedisperse,
+    form Stokes I, take the fluctuation spectrum along time, and image and
+    threshold every frequency f = 1 .. T // 2 (f = 0 is the steady sky; for
+    a real source flux, f and T - f carry the same signal).
+
+    Readings: the DM loop stays outside (a periodic source is dispersed too);
+    the segment length T is the transform length (zero-filled tail as in
+    dedisperse); widths do not apply.  select: optional set of (dm_idx, f).
+    Returns (stats, candidates, images): stats (i, f) -> (peak, X, Y, sigma,
+    snr) of the amplitude image; candidates (i, f, X, Y, snr, peak, sigma) in
+    (i, f) order for snr > threshold.
+    """
+    vis = as_complex(vis)
+    T = vis.shape[0]
+    N = plan.npix
+    stats, cands, images = {}, [], {}
+    dm_set = range(len(plan.dms)) if select is None else sorted({s[0] for s in select})
+    for i in dm_set:
+        F = time_spectrum(stokes_i(dedisperse(vis, plan.delays[i])))
+        for f in range(1, T // 2 + 1):
+            if select is not None and (i, f) not in select:
+                continue
+            G = grid(F[f], plan.iu, plan.iv, plan.valid, N)
+            A = np.abs(complex_image(G, plan.W))
+            st = amplitude_stats(A)
+            stats[(i, f)] = st
+            if keep_images:
+                images[(i, f)] = A
+            peak, x, y, sigma, snr = st
+            if snr > plan.threshold:
+                cands.append((i, f, x, y, snr, peak, sigma))
+    return stats, cands, images

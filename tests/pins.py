@@ -598,6 +598,121 @@ def check_spectrum_pulse(o):
     assert np.mean(away) < 0.5 * 0.5, away
 
 
+# ---------------------------------------------------------------- periodicity search
+
+def check_time_spectrum(o):
+    """The fluctuation spectrum is the 1/T-normalised forward DFT along time:
+    brute force on a short series; a steady source sits in bin 0; a comb of
+    pulses every P integrations has A / P in every multiple of T / P and
+    nothing else."""
+    rng = np.random.default_rng(4)
+    T = 12
+    x = rng.standard_normal((T, 3)) + 1j * rng.standard_normal((T, 3))
+    F = o.time_spectrum(x)
+    for f in range(T):
+        want = sum(x[t] * np.exp(-2j * np.pi * f * t / T) for t in range(T)) / T
+        assert np.max(np.abs(F[f] - want)) < 1e-12, f
+    F = o.time_spectrum(np.full((16, 2), 0.4 - 0.1j))
+    assert np.max(np.abs(F[0] - (0.4 - 0.1j))) < 1e-15 and np.max(np.abs(F[1:])) < 1e-15
+    comb = np.zeros((24, 1), complex)
+    comb[3::6] = 1.5
+    F = o.time_spectrum(comb)
+    for f in range(24):
+        want = 1.5 / 6 if f % 4 == 0 else 0.0
+        assert abs(abs(F[f, 0]) - want) < 1e-14, f
+
+
+def check_complex_image(o):
+    """The complex image: brute-force inverse DFT on a small grid, and its
+    real and imaginary parts are the real images of G and -iG."""
+    rng = np.random.default_rng(6)
+    N = 16
+    G = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    I = o.complex_image(G, 7)
+    ky, kx = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    for Y, X in [(0, 0), (8, 8), (3, 12), (15, 1)]:
+        want = np.sum(G * np.exp(2j * np.pi * (kx * (X - N // 2) + ky * (Y - N // 2)) / N)) / 7
+        assert abs(I[Y, X] - want) < 1e-12, (X, Y)
+    assert np.max(np.abs(I.real - o.image(G, 7))) < 1e-12
+    assert np.max(np.abs(I.imag - o.image(-1j * G, 7))) < 1e-12
+
+
+def check_amplitude_stats(o):
+    """sqrt(2 ln 2) is the median of a unit Rayleigh amplitude (scipy as the
+    library special case); the estimate recovers the per-quadrature noise of
+    a complex Gaussian field; ties go to the lowest index."""
+    from scipy import stats as sst
+    assert abs(o.RAYLEIGH_MEDIAN - sst.rayleigh.median()) < 1e-12
+    rng = np.random.default_rng(12)
+    A = np.abs(0.3 * (rng.standard_normal((512, 512)) + 1j * rng.standard_normal((512, 512))))
+    peak, x, y, sigma, snr = o.amplitude_stats(A)
+    assert abs(sigma / 0.3 - 1) < 0.01, sigma
+    assert peak == A.max() and A[y, x] == peak
+    B = np.ones((8, 8))
+    B[5, 2] = B[2, 6] = 3.0
+    assert o.amplitude_stats(B)[1:3] == (6, 2)
+    assert o.amplitude_stats(np.zeros((4, 4)))[4] == 0.0
+
+
+def _periodic_case(o, T=32, dms=(0.0, 40.0)):
+    from rfgen import synth
+    uvw = synth.baseline_uvw(synth.y_array_positions(10))
+    f = centres(1.0, 2.0, 16)
+    N = 64
+    du = synth.default_cell_size(uvw, f, N)
+    plan = o.Plan(f, uvw, 0.005, np.array(dms), [1], N, du, du, nint=T)
+    return plan, uvw, f, N, du
+
+
+def check_periodic_pulse_train(o):
+    """A noise-free train of pulses every P = 8 integrations from the phase
+    centre, with different flux in the two polarisations, at DM 0: every
+    harmonic f = 4, 8, 12, 16 images to the Stokes I amplitude over P at
+    pixel (N/2, N/2); the frequencies searched are 1 .. T/2."""
+    plan, uvw, f, N, du = _periodic_case(o)
+    vis = np.zeros((32, uvw.shape[0], 16, 2), complex)
+    vis[2::8, :, :, 0] = 1.2
+    vis[2::8, :, :, 1] = 0.4
+    stats, cands, _ = o.periodic_search(vis, plan)
+    assert sorted({k[1] for k in stats}) == list(range(1, 17))
+    for fb in (4, 8, 12, 16):
+        peak, x, y, sigma, snr = stats[(0, fb)]
+        assert (x, y) == (N // 2, N // 2) and abs(peak - 0.8 / 8) < 1e-12, (fb, peak)
+    assert stats[(0, 5)][0] < 1e-12
+
+
+def check_periodic_dispersed(o):
+    """A dispersed pulse train (DM 40, P = 8, from pixel (x0, y0), in
+    noise) is found at its DM trial and fundamental frequency, at its pixel,
+    and not at DM 0 with the same strength."""
+    from rfgen import synth
+    plan, uvw, f, N, du = _periodic_case(o)
+    rng = np.random.default_rng(3)
+    vis = 0.05 * (rng.standard_normal((32, uvw.shape[0], 16, 2)) + 1j * rng.standard_normal((32, uvw.shape[0], 16, 2)))
+    x0, y0 = N // 2 + 4, N // 2 - 3
+    l, m = synth.pixel_to_lm(x0, y0, N, du, du)
+    for t0 in range(1, 32, 8):
+        synth.add_pulse(vis, uvw, f, 0.005, 4.15e-3, 40.0, t0, 1, l, m, 1.0)
+    stats, cands, _ = o.periodic_search(vis, plan)
+    peak, x, y, sigma, snr = stats[(1, 4)]
+    assert (x, y) == (x0, y0) and snr > 20, (x, y, snr)
+    assert (1, 4, x0, y0) in [c[:4] for c in cands]
+    assert stats[(0, 4)][4] < 0.6 * snr
+
+
+def check_periodic_noise_sigma(o):
+    """Noise only: the per-quadrature noise of a frequency's image is
+    (2 T W)^-1/2 for unit complex noise per polarisation (the fluctuation
+    spectrum divides by T), recovered to 5%."""
+    plan, uvw, f, N, du = _periodic_case(o, T=16, dms=(0.0,))
+    rng = np.random.default_rng(21)
+    vis = rng.standard_normal((16, uvw.shape[0], 16, 2)) + 1j * rng.standard_normal((16, uvw.shape[0], 16, 2))
+    stats, _, _ = o.periodic_search(vis, plan, select={(0, 3), (0, 7)})
+    want = (2 * 16 * plan.W) ** -0.5
+    for key, st in stats.items():
+        assert abs(st[3] / want - 1) < 0.05, (key, st[3], want)
+
+
 # ---------------------------------------------------------------- layout
 
 def check_table1_layout():
@@ -617,5 +732,7 @@ ALL_CHECKS = [
     check_noise_sigma, check_subtract_mean, check_inject_boxcar, check_inject_fractional,
     check_inject_dispersion, check_inject_phase, check_inject_flux, check_inject_images_at_pixel,
     check_inject_storage_rounding, check_inject_order, check_cutout, check_spectrum_splits_pixel,
-    check_spectrum_point_source, check_spectrum_pulse,
+    check_spectrum_point_source, check_spectrum_pulse, check_time_spectrum, check_complex_image,
+    check_amplitude_stats, check_periodic_pulse_train, check_periodic_dispersed,
+    check_periodic_noise_sigma,
 ]

@@ -241,6 +241,48 @@ def _cutout_off_by_one(img, x, y, half):
     return ro.candidate_cutout(img, x, y + 1, half)
 
 
+def _tspec_unnormalised(vi):                         # 1/T dropped
+    return np.fft.fft(np.asarray(vi, complex), axis=0)
+
+
+def _tspec_inverse(vi):                              # exp(+2 pi i f t / T)
+    T = vi.shape[0]
+    return np.fft.ifft(np.asarray(vi, complex), axis=0)
+
+
+def _cimage_real(G, W):                              # real part only
+    return ro.image(G, W).astype(complex)
+
+
+def _astats_gaussian(A):                             # transient sigma estimator
+    p, x, y, _, _ = ro.amplitude_stats(A)
+    s = 1.4826 * float(np.median(A))
+    return p, x, y, s, (p / s if s else 0.0)
+
+
+def _periodic_with(zero_freq=False, first_pol=False, no_dd=False):
+    def search(vis, plan, select=None, keep_images=False):
+        vis = ro.as_complex(vis)
+        T = vis.shape[0]
+        stats, cands = {}, []
+        for i in range(len(plan.dms)):
+            d = np.zeros_like(plan.delays[i]) if no_dd else plan.delays[i]
+            dd = ro.dedisperse(vis, d)
+            vi = dd[..., 0] if first_pol else ro.stokes_i(dd)
+            F = ro.time_spectrum(vi)
+            freqs = range(0, T // 2) if zero_freq else range(1, T // 2 + 1)
+            for f in freqs:
+                if select is not None and (i, f) not in select:
+                    continue
+                G = ro.grid(F[f], plan.iu, plan.iv, plan.valid, plan.npix)
+                st = ro.amplitude_stats(np.abs(ro.complex_image(G, plan.W)))
+                stats[(i, f)] = st
+                if st[4] > plan.threshold:
+                    cands.append((i, f, st[1], st[2], st[4], st[0], st[3]))
+        return stats, cands, {}
+    return search
+
+
 MUTANTS = {
     "mean over baselines": dict(subtract_mean=_mean_over_baselines),
     "mean unbiased": dict(subtract_mean=_mean_unbiased),
@@ -280,6 +322,13 @@ MUTANTS = {
     "spectrum rows shifted": dict(candidate_spectrum=_spectrum_with(shift=1)),
     "cutout transposed": dict(candidate_cutout=_cutout_transposed),
     "cutout off by one": dict(candidate_cutout=_cutout_off_by_one),
+    "time spectrum unnormalised": dict(time_spectrum=_tspec_unnormalised),
+    "time spectrum inverse": dict(time_spectrum=_tspec_inverse),
+    "complex image real part": dict(complex_image=_cimage_real),
+    "amplitude sigma gaussian": dict(amplitude_stats=_astats_gaussian),
+    "periodic includes f=0": dict(periodic_search=_periodic_with(zero_freq=True)),
+    "periodic first pol": dict(periodic_search=_periodic_with(first_pol=True)),
+    "periodic not dedispersed": dict(periodic_search=_periodic_with(no_dd=True)),
 }
 
 
