@@ -397,6 +397,37 @@ rf_status rf_noise(const rf_plan *plan, uint64_t seed, uint32_t stream_id, int64
                    void *d_vis, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Periodicity search (section 3.1 footnote: a time segment is Fourier
+ * transformed to frequencies and each frequency imaged; Figure 2 caption: a
+ * modification of the innermost loop).
+ * ------------------------------------------------------------------------ */
+
+/* Workspace of rf_search_periodic: the fluctuation spectrum of one DM trial
+ * (nint/2 x nbl x nchan complex64), one batch of frequency grids, images and
+ * amplitude images, the imaging scratch.  RF_ERANGE unless nint is a power
+ * of two in [2, 8192]. */
+rf_status rf_periodic_workspace_bytes(const rf_plan *plan, size_t *bytes);
+
+/* For every DM trial i of the plan: the segment is dedispersed (zero past its
+ * end), Stokes I formed, and the fluctuation spectrum taken along time per
+ * (baseline, channel): F[f] = (1/T) sum_t V_I[t] exp(-2 pi i f t / T), T =
+ * nint.  Each frequency f = 1 .. T/2 is gridded like an integration and
+ * imaged without taking the real part: I_f = (1/W) sum G e^{+2 pi i (...)/N}
+ * (complex).  Its amplitude |I_f| gives peak (ties to the lowest y*N + x),
+ * sigma = lower median of |I_f| / sqrt(2 ln 2) (the noise per quadrature of a
+ * complex Gaussian image) and snr = peak / sigma; a candidate row is written
+ * when snr > threshold.  Rows use rf_candidate with width_idx = -1 and
+ * t_int = f; peak is the amplitude (the candidate window [t_begin, t_end)
+ * does not apply).  d_stats (nullable) receives [ndm][nint/2] stats, row f-1.
+ * *d_ncand is set to the true count (rows beyond cap dropped).  Widths are
+ * not used.  Asynchronous on `stream`.  RF_EINVAL on NULL, RF_ERANGE if
+ * nint is not a power of two in [2, 8192] or cap < 0, RF_EWORKSPACE if
+ * ws_bytes is too small. */
+rf_status rf_search_periodic(const rf_plan *plan, const void *d_vis, rf_candidate *d_cand,
+                             int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats, void *d_ws,
+                             size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Second-tier candidate products (section 3.1: candidates above a second,
  * higher threshold, typically 7 sigma, get visualisations; section 3.3: the
  * candidate's image and spectrum).

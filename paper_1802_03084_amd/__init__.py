@@ -336,6 +336,30 @@ class Plan:
             return cand, ncand, stats
         return self._collect(cand, ncand, stats, cap)
 
+    def periodic_workspace_bytes(self):
+        n = _lib.c_size(0)
+        _lib.check(_lib.load().rf_periodic_workspace_bytes(self._h, ctypes.byref(n)),
+                   "rf_periodic_workspace_bytes")
+        return n.value
+
+    def search_periodic(self, vis, cap=65536, with_stats=False, ws=None, stream=None):
+        """rf_search_periodic: candidate rows (width_idx = -1, t_int = the
+        frequency bin f), the true count and, with stats, the per-(DM, f)
+        amplitude statistics [ndm * nint/2] (row i * nint/2 + f - 1)."""
+        torch = _torch()
+        self._check_vis(vis, self.nint)
+        if ws is None:
+            ws = torch.empty(max(1, self.periodic_workspace_bytes()), dtype=torch.uint8,
+                             device=self.device)
+        cand = torch.empty((max(cap, 1), 8), dtype=torch.int32, device=self.device)
+        ncand = torch.zeros(1, dtype=torch.int32, device=self.device)
+        nst = self.ndm * (self.nint // 2)
+        stats = torch.empty((max(nst, 1), 5), dtype=torch.int32, device=self.device) if with_stats else None
+        _lib.check(_lib.load().rf_search_periodic(self._h, _ptr(vis), _ptr(cand), int(cap), _ptr(ncand),
+                                                  _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)),
+                   "rf_search_periodic")
+        return self._collect(cand, ncand, stats, cap)
+
     def profile_segment(self, vis, cap=65536, ws=None, stream=None, concurrent=False):
         """rf_search_segment_profile: one fused search with every kernel launch
         event-timed.  concurrent=False runs every launch in order on one stream

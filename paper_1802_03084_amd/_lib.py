@@ -117,6 +117,8 @@ SIGNATURES = {
     "rf_subtract_mean": (c_i32, [c_vp, c_vp, c_vp]),
     "rf_inject": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_vp, c_vp]),
     "rf_noise": (c_i32, [c_vp, ctypes.c_uint64, ctypes.c_uint32, c_i64, c_vp, c_vp]),
+    "rf_periodic_workspace_bytes": (c_i32, [c_vp, ctypes.POINTER(c_size)]),
+    "rf_search_periodic": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_size, c_vp]),
     "rf_products_workspace_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_size)]),
     "rf_candidate_products": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp,
                                       c_size, c_vp]),

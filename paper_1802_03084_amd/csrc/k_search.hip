@@ -6,7 +6,10 @@
 // y*N + x) and histograms the top 11 bits of |img|; passes 2 and 3 refine the
 // bin holding the order statistic of rank floor((N*N - 1) / 2) on the next 11
 // and the last 9 bits.  For non-negative IEEE floats the bit pattern orders
-// like the value, so the three bins name the exact lower median.
+// like the value, so the three bins name the exact lower median.  sigma is
+// that median times a scale: 1.4826 for the images of the transient search
+// (MAD about zero of a Gaussian), 1/sqrt(2 ln 2) for the amplitude images of
+// the periodicity search (the Rayleigh median).
 #include "rf_internal.h"
 
 namespace {
@@ -76,7 +79,7 @@ __global__ __launch_bounds__(kNT) void k_search(const float *__restrict__ img, i
                                                rf_tag_gen gen, rf_image_stats *__restrict__ stats,
                                                rf_candidate *__restrict__ cand, int cap,
                                                int32_t *__restrict__ ncand, float thr,
-                                               int t_begin, int t_end) {
+                                               int t_begin, int t_end, float sigma_scale) {
   __shared__ uint32_t hist[kBins];
   __shared__ uint32_t wsum[kWaves];
   __shared__ uint32_t sel[2];
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(kNT) void k_search(const float *__restrict__ img, i
         pi = bi_s[w];
       }
     const float med = __uint_as_float((pre2 << 9) | sel[0]);
-    const float sigma = 1.4826f * med;
+    const float sigma = sigma_scale * med;
     const float snr = sigma > 0.f ? pv / sigma : 0.f;
     const int x = pi % npix, y = pi / npix;
     if (stats) {
@@ -221,18 +224,26 @@ rf_status launch_zero_i32(int32_t *p, int n, hipStream_t s) {
   return RF_OK;
 }
 
-rf_status launch_search(const rf_plan *p, const float *img, int nimg, const rf_image_tag *tags,
-                        const rf_tag_gen *gen, rf_image_stats *stats, rf_candidate *cand,
-                        int cap, int32_t *ncand, hipStream_t s) {
+rf_status launch_search_ex(const rf_plan *p, const float *img, int nimg,
+                           const rf_image_tag *tags, const rf_tag_gen *gen, rf_image_stats *stats,
+                           rf_candidate *cand, int cap, int32_t *ncand, float sigma_scale,
+                           int t_begin, int t_end, hipStream_t s) {
   if (nimg <= 0) return RF_OK;
   if (gen) {
     k_search<true><<<nimg, kNT, 0, s>>>(img, p->npix, nullptr, *gen, stats, cand, cap, ncand,
-                                        p->threshold, p->t_begin, p->t_end);
+                                        p->threshold, t_begin, t_end, sigma_scale);
   } else {
     rf_tag_gen none{0, 0, 1, 0};
     k_search<false><<<nimg, kNT, 0, s>>>(img, p->npix, tags, none, stats, cand, cap, ncand,
-                                         p->threshold, p->t_begin, p->t_end);
+                                         p->threshold, t_begin, t_end, sigma_scale);
   }
   RF_HIP_TRY(hipGetLastError());
   return RF_OK;
+}
+
+rf_status launch_search(const rf_plan *p, const float *img, int nimg, const rf_image_tag *tags,
+                        const rf_tag_gen *gen, rf_image_stats *stats, rf_candidate *cand,
+                        int cap, int32_t *ncand, hipStream_t s) {
+  return launch_search_ex(p, img, nimg, tags, gen, stats, cand, cap, ncand, 1.4826f, p->t_begin,
+                          p->t_end, s);
 }

@@ -423,6 +423,26 @@ rf_status rf_inject(const rf_plan *p, const rf_mock *h_mocks, int32_t nmock, int
   return launch_inject(p, h_mocks, nmock, t_first, d_vis, (hipStream_t)stream);
 }
 
+static bool periodic_shape_ok(const rf_plan *p) {
+  return p->nint >= 2 && p->nint <= 8192 && (p->nint & (p->nint - 1)) == 0;
+}
+
+rf_status rf_periodic_workspace_bytes(const rf_plan *p, size_t *bytes) {
+  if (!p || !bytes) return RF_EINVAL;
+  if (!periodic_shape_ok(p)) return RF_ERANGE;
+  *bytes = periodic_ws_bytes(p);
+  return RF_OK;
+}
+
+rf_status rf_search_periodic(const rf_plan *p, const void *d_vis, rf_candidate *d_cand,
+                             int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats, void *d_ws,
+                             size_t ws_bytes, void *stream) {
+  if (!p || !d_vis || !d_ncand || !d_ws || (cap > 0 && !d_cand)) return RF_EINVAL;
+  if (cap < 0 || !periodic_shape_ok(p)) return RF_ERANGE;
+  if (ws_bytes < periodic_ws_bytes(p)) return RF_EWORKSPACE;
+  return run_periodic(p, d_vis, d_cand, cap, d_ncand, d_stats, d_ws, (hipStream_t)stream);
+}
+
 rf_status rf_products_workspace_bytes(const rf_plan *p, int32_t nspec, size_t *bytes) {
   if (!p || !bytes) return RF_EINVAL;
   if (nspec < 1 || nspec > 4096) return RF_ERANGE;

@@ -120,6 +120,10 @@ struct rf_tag_gen {       // implicit tags: image n -> (dm_idx, width_idx, (k0 +
 rf_status launch_search(const rf_plan *p, const float *img, int nimg, const rf_image_tag *tags,
                         const rf_tag_gen *gen, rf_image_stats *stats, rf_candidate *cand,
                         int cap, int32_t *ncand, hipStream_t s);
+rf_status launch_search_ex(const rf_plan *p, const float *img, int nimg,
+                           const rf_image_tag *tags, const rf_tag_gen *gen, rf_image_stats *stats,
+                           rf_candidate *cand, int cap, int32_t *ncand, float sigma_scale,
+                           int t_begin, int t_end, hipStream_t s);
 rf_status launch_zero_i32(int32_t *p, int n, hipStream_t s);
 rf_status launch_zero_f32(float *p, size_t nfloat, hipStream_t s);
 
@@ -154,3 +158,8 @@ size_t products_ws_bytes(const rf_plan *p, int nspec);
 rf_status run_products(const rf_plan *p, const void *vis, const rf_candidate *cand, int ncand,
                        int half, int nspec, float *cutout, float *spec, void *ws,
                        hipStream_t s);
+
+// periodicity search (k_periodic.hip)
+size_t periodic_ws_bytes(const rf_plan *p);
+rf_status run_periodic(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
+                       int32_t *ncand, rf_image_stats *stats, void *ws, hipStream_t s);

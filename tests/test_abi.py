@@ -164,3 +164,10 @@ def test_products_arguments_rejected_without_gpu():
     n = ctypes.c_size_t(0)
     assert L.rf_products_workspace_bytes(None, 16, ctypes.byref(n)) == -1
     assert L.rf_candidate_products(None, None, None, 0, 8, 16, None, None, None, 0, None) == -1
+
+
+def test_periodic_arguments_rejected_without_gpu():
+    L = lib()
+    n = ctypes.c_size_t(0)
+    assert L.rf_periodic_workspace_bytes(None, ctypes.byref(n)) == -1
+    assert L.rf_search_periodic(None, None, None, 0, None, None, None, 0, None) == -1
