@@ -34,7 +34,7 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X fp32 vector, published
 # 524,300 KiB for 1 GiB read: x2; WRITE_SIZE 1,049,000 KiB for 1 GiB written:
 # x1).  Valid only for the kernel source with this digest (column kernel
 # section of k_fused.hip, fft.h, rf_internal.h); null once it changes.
-COLS_TRAFFIC = {"digest": "18fd00787aedc980", "fetch_kib": 56810.0, "write_kib": 1276.0,
+COLS_TRAFFIC = {"digest": "7335f17ecf25d542", "fetch_kib": 56810.0, "write_kib": 1276.0,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -45,8 +45,11 @@ def cols_kernel_digest():
     a = k.index("// ------------------------------------------------------------------ columns")
     b = k.index("// ------------------------------------------------------------------ select")
     h = hashlib.sha256(k[a:b].encode())
-    for f in ("fft.h", "rf_internal.h"):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(csrc, "fft.h"), "rb").read())
+    # from the internal header only the device helpers the kernel calls (the
+    # plan struct and host declarations are not part of the kernel's code)
+    r = open(os.path.join(csrc, "rf_internal.h")).read()
+    h.update(r[r.index("// Factor of the paired Hermitian"):r.index("#define RF_HIP_TRY")].encode())
     return h.hexdigest()[:16]
 
 
@@ -200,6 +203,60 @@ def event_time(fn, reps, stream):
     return start.elapsed_time(end) / reps * 1e-3  # seconds per call
 
 
+def large_leg(ndm, steps):
+    """The large workload (351 baselines, 8192 x 1 ms, 1024 channels over
+    2-4 GHz, widths 1..32, 2048^2 images) over ndm of its 400 DM trials spread
+    evenly over the grid plus the five pulses' trials (every DM trial costs
+    the same), generated on the device with the pulses,
+    in CF16 and CF32 storage.  Reports images/s and the projected time and
+    real-time factor of the full 400-trial segment."""
+    import numpy as np
+    import torch
+    import rfgen
+    import paper_1802_03084_amd as rf
+    from paper_1802_03084_amd import mock
+    p = rfgen.large()
+    full_ndm = len(p.dms)
+    keep = sorted(set(np.linspace(0, full_ndm - 1, ndm).round().astype(int).tolist())
+                  | {q.dm_idx for q in p.pulses})
+    mocks = p.mocks()
+    pulses = [(keep.index(q.dm_idx), q.width_idx, q.t0, q.x, q.y) for q in p.pulses if q.dm_idx in keep]
+    du, dv = p.cell()
+    seg_s = p.nint * p.tint_s
+    out = {"workload": f"large: {p.nbl} baselines, {p.nint} x {p.tint_s * 1e3:g} ms, {p.nchan} chans "
+                       f"{p.f_lo_ghz}-{p.f_hi_ghz} GHz, widths {p.widths}, {p.npix}^2; {len(keep)} of "
+                       f"{full_ndm} DM trials"}
+    for name, dt in (("cf16", rf.RF_CF16), ("cf32", rf.RF_CF32)):
+        plan = rf.Plan(p.freq(), p.uvw(), p.tint_s, p.dms[keep], p.widths, p.npix, du, dv,
+                       nint=p.nint, npol=p.npol, vis_dtype=dt, kdm=p.kdm, threshold=p.threshold)
+        t = time.perf_counter()
+        vis = mock.synthesize(plan, p.seed, mocks)
+        torch.cuda.synchronize()
+        gen_s = time.perf_counter() - t
+        ws = plan.workspace(rf.RF_OP_SEGMENT)
+        rows, n, _ = plan.search_segment(vis, ws=ws)  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            rows, n, _ = plan.search_segment(vis, ws=ws)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t) / steps
+        keys = {tuple(int(r[f]) for f in ("dm_idx", "width_idx", "t_int", "x", "y")) for r in rows}
+        per_dm = dt_s / len(keep)
+        out[name] = {"images_per_step": plan.n_images, "ms_per_step": round(dt_s * 1e3, 1),
+                     "images_per_s": round(plan.n_images / dt_s, 1),
+                     "ms_per_dm_trial": round(per_dm * 1e3, 2),
+                     "full_segment_s": round(per_dm * full_ndm, 2),
+                     "full_segment_rtf": round(seg_s / (per_dm * full_ndm), 3),
+                     "pulses_recovered": f"{sum(k in keys for k in pulses)}/{len(pulses)}",
+                     "generate_s": round(gen_s, 2)}
+        log(f"large {name}: {plan.n_images / dt_s:.0f} images/s, {per_dm * 1e3:.1f} ms per DM trial, "
+            f"full segment {per_dm * full_ndm:.1f} s (RTF {seg_s / (per_dm * full_ndm):.3f})")
+        del vis, ws, plan
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +277,10 @@ def main():
     ap.add_argument("--serving-segments", type=int, default=12, help="segments per subarray")
     ap.add_argument("--serving-slots", type=int, default=3)
     ap.add_argument("--serving-only", action="store_true", help="run only the serving legs")
+    ap.add_argument("--no-periodic", action="store_true", help="skip the periodicity-search leg")
+    ap.add_argument("--large", type=int, default=0, metavar="NDM",
+                    help="only time the large workload (8192 x 1 ms, 1024 chans, 2048^2) over NDM "
+                         "of its 400 DM trials, generated on the device, in both storages")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (a plain copy kernel of known size, "
                          "to scale the HBM byte counters) and report its bandwidth")
@@ -253,6 +314,10 @@ def main():
         dt = t0.elapsed_time(t1) / reps * 1e-3
         print(json.dumps({"copy_bytes": n, "read_plus_write_GBps": round(2 * n / dt / 1e9, 1),
                           "avg_us": round(dt * 1e6, 1)}), flush=True)
+        return
+
+    if args.large:
+        print(json.dumps({"large": large_leg(args.large, args.steps)}), flush=True)
         return
 
     if args.serving_only:
@@ -398,6 +463,28 @@ def main():
         log(f"plain step chain: {tp:.2f}s/step, {plan.n_images / tp:.0f} images/s, same candidates {keys_p == keys}")
         del wsp
 
+    periodic = None
+    if not args.no_periodic and (p.nint & (p.nint - 1)) == 0:
+        del ws
+        torch.cuda.empty_cache()
+        wsp = torch.empty(plan.periodic_workspace_bytes(), dtype=torch.uint8, device=dev)
+        plan.search_periodic(dvis, cap=cap, ws=wsp)  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rows_q, n_q, _ = plan.search_periodic(dvis, cap=cap, ws=wsp)
+        torch.cuda.synchronize()
+        tq = time.perf_counter() - t
+        nimg = len(p.dms) * (p.nint // 2)
+        periodic = {"path": "rf_search_periodic (time FFT per DM, one complex image per fluctuation "
+                            "frequency 1..T/2, amplitude statistics)",
+                    "images_per_step": nimg, "ms_per_step": round(tq * 1e3, 1),
+                    "images_per_s": round(nimg / tq, 1), "rtf": round(seg_s / tq, 3),
+                    "candidates": n_q}
+        log(f"periodicity search: {tq:.2f}s/step, {nimg / tq:.0f} complex images/s, RTF {seg_s / tq:.2f}, "
+            f"{n_q} candidates")
+        del wsp
+        ws = None
+
     serving = None
     if not args.no_serving:
         del ws, dvis
@@ -432,6 +519,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serving": serving,
+        "periodic": periodic,
     }
     print(json.dumps(out), flush=True)
 
