@@ -89,8 +89,9 @@ __device__ __forceinline__ void load_pols(const __half2 *vis, size_t e, int P, f
 // Dedisperse + boxcar-resample to every width in `ws` + Stokes I, one thread
 // per (baseline, channel) walking a chunk of integrations that starts at a
 // multiple of every width.  Sums run per polarisation in increasing time and
-// are divided by the width before the polarisations are averaged, exactly as
-// rf_resample followed by rf_grid's Stokes I.  Output per width:
+// are scaled by 1/w (the float reciprocal, exact for powers of two) before
+// the polarisations are averaged, exactly as rf_resample followed by
+// rf_grid's Stokes I.  Output per width:
 // VI_w[k][bc], coalesced along bc.
 template <typename Ein, int P>
 __global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis,
@@ -102,12 +103,15 @@ __global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis
   const int t0 = blockIdx.y * tchunk;
   const int t1 = min(nint, t0 + tchunk);
   float2 a0[kMaxW], a1[kMaxW];
-  int cnt[kMaxW];
+  int cnt[kMaxW], kout[kMaxW];
+  float inv[kMaxW];  // 1/w: exact for powers of two, so the product is the quotient
 #pragma unroll
   for (int j = 0; j < kMaxW; ++j) {
     a0[j] = make_float2(0.f, 0.f);
     a1[j] = a0[j];
     cnt[j] = 0;
+    inv[j] = j < ws.nw ? 1.0f / (float)ws.w[j] : 0.f;
+    kout[j] = j < ws.nw ? t0 / ws.w[j] : 0;  // t0 is a multiple of every width
   }
   constexpr int U = 8;  // integrations loaded ahead: U loads in flight per thread
   for (int tb = t0; tb < t1; tb += U) {
@@ -136,17 +140,17 @@ __global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis
             a1[j].y += v1.y;
           }
           if (++cnt[j] == ws.w[j]) {
-            const int k = (t + 1) / ws.w[j] - 1;
-            const float fw = (float)ws.w[j];
+            const float iw = inv[j];
             float2 vi;
             if (P == 2) {
-              const float r0x = a0[j].x / fw, r0y = a0[j].y / fw;
-              const float r1x = a1[j].x / fw, r1y = a1[j].y / fw;
+              const float r0x = a0[j].x * iw, r0y = a0[j].y * iw;
+              const float r1x = a1[j].x * iw, r1y = a1[j].y * iw;
               vi = make_float2((r0x + r1x) * 0.5f, (r0y + r1y) * 0.5f);
             } else {
-              vi = make_float2(a0[j].x / fw, a0[j].y / fw);
+              vi = make_float2(a0[j].x * iw, a0[j].y * iw);
             }
-            ws.out[j][(size_t)k * nbc + bc] = vi;
+            ws.out[j][(size_t)kout[j] * nbc + bc] = vi;
+            ++kout[j];
             a0[j] = make_float2(0.f, 0.f);
             a1[j] = a0[j];
             cnt[j] = 0;

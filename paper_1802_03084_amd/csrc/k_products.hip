@@ -56,8 +56,9 @@ __global__ __launch_bounds__(kThreads) void k_gather_rs(const E *__restrict__ in
         acc.y += x.y;
       }
     }
-    acc.x /= (float)w;
-    acc.y /= (float)w;
+    const float iw = 1.0f / (float)w;  // as the search's resampling
+    acc.x *= iw;
+    acc.y *= iw;
   }
   out[(size_t)s * nelem + e] = acc;
 }

@@ -9,7 +9,8 @@
 // once.
 //
 // Resampling (Figure 2's loop over sampling times) is a decimating boxcar mean
-// accumulated in float32 in increasing sample order.
+// accumulated in float32 in increasing sample order and scaled by the float
+// reciprocal of the width (exact for powers of two).
 //
 // Mean subtraction (section 3.1: the mean visibility in time is subtracted on
 // timescales below the fringe rate, which removes constant sources) works in
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(kThreads) void k_resample(const Ein *__restrict__ i
   if (e >= nelem) return;
   const int k0 = blockIdx.y * kTChunk;
   const int k1 = min(nout, k0 + kTChunk);
-  const float fw = (float)width;
+  const float iw = 1.0f / (float)width;  // exact for powers of two
   for (int k = k0; k < k1; ++k) {
     const size_t base = (size_t)k * width * nelem + e;
     float2 acc = make_float2(0.f, 0.f);
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(kThreads) void k_resample(const Ein *__restrict__ i
       acc.x += x.x;
       acc.y += x.y;
     }
-    out[(size_t)k * nelem + e] = make_float2(acc.x / fw, acc.y / fw);
+    out[(size_t)k * nelem + e] = make_float2(acc.x * iw, acc.y * iw);
   }
 }
 
