@@ -169,7 +169,8 @@ __global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis
 // samples in LDS with all loads in flight, then one thread per cell sums them
 // in contributor order.  All blocks of one image group run on one XCD (blocks
 // are dealt to the eight XCDs round robin), so the group's samples stay in
-// that XCD's L2.
+// that XCD's L2; a batch of fewer than eight groups spreads each group's
+// blocks over 8 / groups XCDs instead.
 constexpr int kCellThreads = 256;
 constexpr int kCellImgs = 4;       // images per workgroup: contributor indices loaded once
 constexpr int kCellBlock = 1024;   // contributors staged per workgroup
@@ -177,11 +178,18 @@ constexpr int kCellBlock = 1024;   // contributors staged per workgroup
 __global__ __launch_bounds__(kCellThreads) void k_cellsum(
     const float2 *__restrict__ vi, int nbc, int k0, int nimg, int n_cells, int n_cblk,
     const int32_t *__restrict__ cblk, const int32_t *__restrict__ coff,
-    const int32_t *__restrict__ contrib, float2 *__restrict__ cv) {
+    const int32_t *__restrict__ contrib, float2 *__restrict__ cv, int rep) {
   __shared__ float2 val[kCellBlock * kCellImgs];
   const int b = blockIdx.x, xcd = b & 7, local = b >> 3;
-  const int g = (local / n_cblk) * 8 + xcd;  // group of kCellImgs images within the batch
-  const int blk = local % n_cblk;
+  int g, blk;  // group of kCellImgs images within the batch, cell block
+  if (rep == 1) {  // at least eight groups: every block of a group on one XCD
+    g = (local / n_cblk) * 8 + xcd;
+    blk = local % n_cblk;
+  } else {  // fewer groups: `rep` XCDs share a group's blocks
+    g = xcd / rep;
+    blk = local * rep + xcd % rep;
+    if (blk >= n_cblk) return;
+  }
   const int i0 = g * kCellImgs;
   if (i0 >= nimg) return;
   const int tid = threadIdx.x;
@@ -1042,11 +1050,15 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
   float *list = (float *)(ws + B.list);
   const int npb = (pbn + sh.pbw - 1) / sh.pbw;
   const int nimg_b = std::min(2 * pbn, nimg_w - 2 * p0);  // images in this batch
-  const int groups = (nimg_b + 8 * kCellImgs - 1) / (8 * kCellImgs);
+  // image groups; with fewer than eight, several XCDs share each group's cell
+  // blocks so that no XCD idles
+  const int ngrp = (nimg_b + kCellImgs - 1) / kCellImgs;
+  const int rep = ngrp >= 8 ? 1 : 8 / ngrp;
+  const int per_xcd = rep == 1 ? (ngrp + 7) / 8 * p->n_cblk : (p->n_cblk + rep - 1) / rep;
   RF_TIMED(tm, RF_K_GRID, s,
-           (k_cellsum<<<(unsigned)(groups * 8 * p->n_cblk), kCellThreads, 0, s>>>(
+           (k_cellsum<<<(unsigned)(8 * per_xcd), kCellThreads, 0, s>>>(
                vi, p->nbl * p->nchan, 2 * p0, nimg_b, p->n_cells, p->n_cblk, p->d_cblk,
-               p->d_ucell_off, p->d_contrib, cv)));
+               p->d_ucell_off, p->d_contrib, cv, rep)));
   RF_TIMED(tm, RF_K_ROWS, s,
            (k_rows_pairs<N><<<(unsigned)(npb * p->n_rp), RowPairCfg<N>::NT, 0, s>>>(
                cv, p->n_cells, nimg_w, p0, pbn, p->d_rp_row, p->d_rp_sa, p->d_rp_sb, p->n_rp,

@@ -3,23 +3,24 @@
 // caption: a modification of the innermost loop).
 //
 // Per DM trial:
-//   1. k_time_fft: the dedispersed Stokes I series of COLS adjacent (baseline,
-//      channel) pairs is loaded into LDS (zero past the end of the segment,
-//      bit-reversed order), transformed along time with radix-2 butterflies
+//   1. k_time_fft_n (T = 64 .. 2048; k_time_fft, radix-2 in LDS, otherwise):
+//      the dedispersed Stokes I series of COLS adjacent (baseline, channel)
+//      pairs (zero past the end of the segment) is transformed along time
 //      (forward, exp(-2 pi i f t / T), float32, twiddles from a float64
 //      table) and frequencies f = 1 .. T/2 are written divided by T, rows of
 //      (baseline, channel) so the gridding reads them contiguously.
 //   2. Per batch of frequencies, k_grid_pf sums each occupied cell's
 //      contributors (the plan's cell-sorted order, fixed summation order) into
-//      two dense grids, G and -iG.  The dense imaging kernels turn that pair
-//      into Re and Im of the complex image (the real image of -iG is the
-//      imaginary part of the image of G).
-//   3. k_amplitude forms |I|; the dense search kernel takes its peak and exact
+//      one dense grid per frequency.  The dense imaging kernels transform it
+//      as one complex image (the pair transform of (G, -iG): Re and Im are
+//      the real images of G and -iG) and write its amplitude |I|.
+//   3. The dense search kernel takes the amplitude image's peak and exact
 //      lower median and thresholds peak / (median / sqrt(2 ln 2)).
 // The transform length is the segment length, a power of two up to 8192.
 #pragma clang fp contract(off)
 
 #include "rf_internal.h"
+#include "fft.h"
 
 #include <hip/hip_fp16.h>
 
@@ -30,23 +31,71 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kLdsPoints = 8192;          // complex points per workgroup (64 KB)
-constexpr size_t kBatchBudget = 1u << 30;  // bytes of grids and images per frequency batch
+// bytes of grids and images per frequency batch: enough frequencies that the
+// per-image search (one workgroup per image) fills the 256 CUs
+constexpr size_t kBatchBudget = (size_t)10 << 30;
 constexpr float kInvRayleighMedian = 0.84932180028801907f;  // 1 / sqrt(2 ln 2)
 
 constexpr size_t kAlign = 256;
 inline size_t aup(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
+// tw[m] = exp(+2 pi i m / T), m < T, from float64
 __global__ void k_time_twiddles(float2 *__restrict__ tw, int T) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= T / 2) return;
+  if (k >= T) return;
   double s, c;
-  sincospi(-2.0 * (double)k / (double)T, &s, &c);
+  sincospi(2.0 * (double)k / (double)T, &s, &c);
   tw[k] = make_float2((float)c, (float)s);
 }
 
 __device__ __forceinline__ float2 load_c(const float2 *p, size_t i) { return p[i]; }
 __device__ __forceinline__ float2 load_c(const __half2 *p, size_t i) {
   return __half22float2(p[i]);
+}
+
+// Lengths 64 .. 2048: the forward transform as the conjugate of the inverse
+// transform of the conjugate input, with the register/LDS FFT of the image
+// columns (ColFft<T>, COLS adjacent (baseline, channel) series per
+// workgroup, tiles dealt to the XCDs in contiguous runs so neighbouring tiles
+// share cache lines).  Each thread's series is tid mod COLS in every pass
+// (NT is a multiple of COLS), so its delay and output column are fixed.
+template <int T, typename E, int P>
+__global__ __launch_bounds__(rf::ColCfg<T>::NT) void k_time_fft_n(
+    const E *__restrict__ vis, float2 *__restrict__ out, const int32_t *__restrict__ delay,
+    const float2 *__restrict__ tw, int nbc, int nchan) {
+  using namespace rf;
+  constexpr int COLS = ColCfg<T>::COLS, NT = ColCfg<T>::NT, S = ColCfg<T>::STRIDE;
+  static_assert(NT % COLS == 0, "a thread's series must be the same in every pass");
+  __shared__ float2 buf[COLS * S];
+  const int ntile = (nbc + COLS - 1) / COLS;
+  const int per = (ntile + 7) >> 3;
+  const int b = blockIdx.x;
+  const int L = (b & 7) * per + (b >> 3);
+  if ((b >> 3) >= per || L >= ntile) return;
+  const int tid = threadIdx.x;
+  const int bc_raw = L * COLS + tid % COLS;
+  const bool col_ok = bc_raw < nbc;
+  const int bc = col_ok ? bc_raw : nbc - 1;
+  const int d = delay[bc % nchan];
+  const float inv_t = 1.0f / (float)T;
+  fft_inverse<ColFft<T>, COLS, NT, S, false>(
+      buf, tw, tid,
+      [&](int, int i) {  // conjugate of the dedispersed Stokes I at time i
+        const int src = i + d;
+        const size_t e = ((size_t)min(src, T - 1) * nbc + bc) * P;
+        float2 v;
+        if (P == 2) {
+          const float2 a = load_c(vis, e), q = load_c(vis, e + 1);
+          v = make_float2((a.x + q.x) * 0.5f, (a.y + q.y) * 0.5f);
+        } else {
+          v = load_c(vis, e);
+        }
+        return (src < T && col_ok) ? make_float2(v.x, -v.y) : make_float2(0.f, 0.f);
+      },
+      [&](int, int y, float2 v) {  // frequency y = 1 .. T/2, conjugated back, over T
+        if (y >= 1 && y <= T / 2 && col_ok)
+          out[(size_t)(y - 1) * nbc + bc] = make_float2(v.x * inv_t, -v.y * inv_t);
+      });
 }
 
 template <typename E, int P>
@@ -90,7 +139,8 @@ __global__ __launch_bounds__(kThreads) void k_time_fft(const E *__restrict__ vis
       const int j = b & (half - 1);
       const int i0 = ((b >> s) << (s + 1)) + j;
       const int i1 = i0 + half;
-      const float2 w = tw[j * tstep];
+      const float2 wp = tw[j * tstep];  // the forward transform uses exp(-i): conjugate
+      const float2 w = make_float2(wp.x, -wp.y);
       const float2 x = lds[i0 * cols + col], y = lds[i1 * cols + col];
       const float2 wy = make_float2(w.x * y.x - w.y * y.y, w.x * y.y + w.y * y.x);
       lds[i0 * cols + col] = make_float2(x.x + wy.x, x.y + wy.y);
@@ -111,7 +161,9 @@ __global__ __launch_bounds__(kThreads) void k_time_fft(const E *__restrict__ vis
   }
 }
 
-// Grid pair (G, -iG) of frequency rows [0, nf) of F (rows of nbc values).
+// Grid of each frequency row [0, nf) of F (rows of nbc values): only the
+// occupied cells are written (the rest of the grids stays zero from the
+// clear at the start of the search: every frequency occupies the same cells).
 __global__ __launch_bounds__(kThreads) void k_grid_pf(const float2 *__restrict__ F, int nbc,
                                                       const int32_t *__restrict__ ucell,
                                                       const int32_t *__restrict__ off,
@@ -129,24 +181,11 @@ __global__ __launch_bounds__(kThreads) void k_grid_pf(const float2 *__restrict__
     acc.x += v.x;
     acc.y += v.y;
   }
-  grid[(size_t)(2 * n) * npix2 + ucell[u]] = acc;
-  grid[(size_t)(2 * n + 1) * npix2 + ucell[u]] = make_float2(acc.y, -acc.x);
-}
-
-__global__ __launch_bounds__(kThreads) void k_amplitude(const float *__restrict__ img,
-                                                        float *__restrict__ amp, size_t npix2,
-                                                        int nf) {
-  const size_t total = npix2 * nf;
-  const size_t step = (size_t)gridDim.x * kThreads;
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < total; i += step) {
-    const size_t n = i / npix2, px = i - n * npix2;
-    const float re = img[(2 * n) * npix2 + px], im = img[(2 * n + 1) * npix2 + px];
-    amp[i] = sqrtf(re * re + im * im);
-  }
+  grid[(size_t)n * npix2 + ucell[u]] = acc;
 }
 
 struct PLayout {
-  size_t tw, F, grid, img, amp, imgws, total;
+  size_t tw, F, grid, amp, imgws, total;
   int nf;
 };
 
@@ -155,24 +194,70 @@ PLayout periodic_layout(const rf_plan *p) {
   const int T = p->nint;
   const size_t n2 = (size_t)p->npix * p->npix;
   const size_t nbc = (size_t)p->nbl * p->nchan;
-  const size_t per_f = 2 * n2 * sizeof(float2) + 2 * n2 * sizeof(float) + n2 * sizeof(float) +
+  const size_t per_f = n2 * sizeof(float2) + n2 * sizeof(float) +
                        (size_t)p->n_rows * p->npix * sizeof(float2);
   L.nf = (int)std::max<size_t>(1, std::min<size_t>((size_t)T / 2, kBatchBudget / per_f));
   size_t o = 0;
   L.tw = o;
-  o += aup(sizeof(float2) * (size_t)std::max(1, T / 2));
+  o += aup(sizeof(float2) * (size_t)std::max(1, T));
   L.F = o;
   o += aup(sizeof(float2) * (size_t)(T / 2) * nbc);
   L.grid = o;
-  o += aup(sizeof(float2) * 2 * n2 * L.nf);
-  L.img = o;
-  o += aup(sizeof(float) * 2 * n2 * L.nf);
+  o += aup(sizeof(float2) * n2 * L.nf);
   L.amp = o;
   o += aup(sizeof(float) * n2 * L.nf);
   L.imgws = o;
   o += aup(image_ws_bytes(p, 2 * L.nf));
   L.total = o;
   return L;
+}
+
+}  // namespace
+
+namespace {
+
+template <typename E, int P>
+rf_status time_fft_e(const rf_plan *p, const E *vis, float2 *F, const int32_t *delay,
+                     const float2 *tw, int T, int log2t, int nbc, int cols, int nblk,
+                     hipStream_t s) {
+  const int nchan = p->nchan;
+#define RF_TFFT(TT)                                                                          \
+  case TT: {                                                                                 \
+    constexpr int C = rf::ColCfg<TT>::COLS;                                                 \
+    const int ntile = (nbc + C - 1) / C;                                                     \
+    k_time_fft_n<TT, E, P><<<(unsigned)((ntile + 7) / 8 * 8), rf::ColCfg<TT>::NT, 0, s>>>( \
+        vis, F, delay, tw, nbc, nchan);                                                      \
+    break;                                                                                   \
+  }
+  switch (T) {
+    RF_TFFT(64)
+    RF_TFFT(128)
+    RF_TFFT(256)
+    RF_TFFT(512)
+    RF_TFFT(1024)
+    RF_TFFT(2048)
+    default:
+      k_time_fft<E, P><<<nblk, kThreads, 0, s>>>(vis, F, delay, tw, T, log2t, nbc, nchan, cols);
+  }
+#undef RF_TFFT
+  RF_HIP_TRY(hipGetLastError());
+  return RF_OK;
+}
+
+rf_status time_fft(const rf_plan *p, const void *vis, float2 *F, const int32_t *delay,
+                   const float2 *tw, int T, int log2t, int nbc, int cols, int nblk,
+                   hipStream_t s) {
+  if (p->vis_dtype == RF_CF32)
+    return p->npol == 2
+               ? time_fft_e<float2, 2>(p, (const float2 *)vis, F, delay, tw, T, log2t, nbc, cols,
+                                       nblk, s)
+               : time_fft_e<float2, 1>(p, (const float2 *)vis, F, delay, tw, T, log2t, nbc, cols,
+                                       nblk, s);
+  return p->npol == 2
+             ? time_fft_e<__half2, 2>(p, (const __half2 *)vis, F, delay, tw, T, log2t, nbc, cols,
+                                      nblk, s)
+             : time_fft_e<__half2, 1>(p, (const __half2 *)vis, F, delay, tw, T, log2t, nbc, cols,
+                                      nblk, s);
 }
 
 }  // namespace
@@ -186,7 +271,6 @@ rf_status run_periodic(const rf_plan *p, const void *vis, rf_candidate *cand, in
   float2 *tw = (float2 *)(base + L.tw);
   float2 *F = (float2 *)(base + L.F);
   float2 *grid = (float2 *)(base + L.grid);
-  float *img = (float *)(base + L.img);
   float *amp = (float *)(base + L.amp);
   float2 *imgws = (float2 *)(base + L.imgws);
   const int T = p->nint;
@@ -199,45 +283,27 @@ rf_status run_periodic(const rf_plan *p, const void *vis, rf_candidate *cand, in
 
   rf_status st = launch_zero_i32(ncand, 1, s);
   if (st != RF_OK) return st;
-  k_time_twiddles<<<(nfreq + kThreads - 1) / kThreads, kThreads, 0, s>>>(tw, T);
+  st = launch_zero_f32((float *)grid, 2 * n2 * (size_t)L.nf, s);  // unoccupied cells stay zero
+  if (st != RF_OK) return st;
+  k_time_twiddles<<<(T + kThreads - 1) / kThreads, kThreads, 0, s>>>(tw, T);
   RF_HIP_TRY(hipGetLastError());
   const int nblk = (nbc + cols - 1) / cols;
   const int bpf = (p->n_cells + kThreads - 1) / kThreads;
   const int no_window_lo = INT32_MIN, no_window_hi = INT32_MAX;
   for (int i = 0; i < p->ndm; ++i) {
     const int32_t *delay = p->d_delay + (size_t)i * p->nchan;
-    if (p->vis_dtype == RF_CF32) {
-      if (p->npol == 2)
-        k_time_fft<float2, 2><<<nblk, kThreads, 0, s>>>((const float2 *)vis, F, delay, tw, T,
-                                                        log2t, nbc, p->nchan, cols);
-      else
-        k_time_fft<float2, 1><<<nblk, kThreads, 0, s>>>((const float2 *)vis, F, delay, tw, T,
-                                                        log2t, nbc, p->nchan, cols);
-    } else {
-      if (p->npol == 2)
-        k_time_fft<__half2, 2><<<nblk, kThreads, 0, s>>>((const __half2 *)vis, F, delay, tw, T,
-                                                         log2t, nbc, p->nchan, cols);
-      else
-        k_time_fft<__half2, 1><<<nblk, kThreads, 0, s>>>((const __half2 *)vis, F, delay, tw, T,
-                                                         log2t, nbc, p->nchan, cols);
-    }
-    RF_HIP_TRY(hipGetLastError());
+    st = time_fft(p, vis, F, delay, tw, T, log2t, nbc, cols, nblk, s);
+    if (st != RF_OK) return st;
     for (int f0 = 0; f0 < nfreq; f0 += L.nf) {
       const int nf = std::min(L.nf, nfreq - f0);
-      st = launch_zero_f32((float *)grid, 2 * 2 * n2 * (size_t)nf, s);
-      if (st != RF_OK) return st;
       if (p->n_cells > 0) {
         k_grid_pf<<<(unsigned)(bpf * nf), kThreads, 0, s>>>(F + (size_t)f0 * nbc, nbc, p->d_ucell,
                                                             p->d_ucell_off, p->d_contrib,
                                                             p->n_cells, bpf, n2, grid);
         RF_HIP_TRY(hipGetLastError());
       }
-      st = launch_image_dense(p, grid, 2 * nf, img, imgws, s);
+      st = launch_image_amplitude(p, grid, nf, amp, imgws, s);
       if (st != RF_OK) return st;
-      const size_t tot = n2 * nf;
-      const int ablk = (int)std::min<size_t>((tot + kThreads - 1) / kThreads, 16384);
-      k_amplitude<<<ablk, kThreads, 0, s>>>(img, amp, n2, nf);
-      RF_HIP_TRY(hipGetLastError());
       // image n of the batch is frequency f0 + 1 + n: tag t_int = f
       const rf_tag_gen gen{i, -1, 1, f0 + 1};
       rf_image_stats *st_out = stats ? stats + (size_t)i * nfreq + f0 : nullptr;

@@ -112,6 +112,10 @@ rf_status launch_grid_dense(const rf_plan *p, const float2 *vis, int nimg, float
 size_t image_ws_bytes(const rf_plan *p, int64_t nimg);
 rf_status launch_image_dense(const rf_plan *p, const float2 *grid, int nimg, float *img,
                              float2 *ws, hipStream_t s);
+// complex images of nimg grids (no Hermitian symmetry), written as amplitudes
+// [nimg][N][N]; ws holds image_ws_bytes(p, 2 * nimg)
+rf_status launch_image_amplitude(const rf_plan *p, const float2 *grid, int nimg, float *amp,
+                                 float2 *ws, hipStream_t s);
 
 // statistics, threshold and candidates
 struct rf_tag_gen {       // implicit tags: image n -> (dm_idx, width_idx, (k0 + n) * w)

@@ -70,9 +70,11 @@ def _compare(g, p, vis_host, dvis, select=None):
     return rows
 
 
-@pytest.mark.parametrize("dtype", [0, 1])
-def test_periodic_small_matches_oracle(torch, dtype):
-    p = rfgen.smallcase(nant=10, nint=32, nchan=48, npix=128, seed=17)
+@pytest.mark.parametrize("dtype,nint", [(0, 32), (1, 32), (0, 64), (1, 256)])
+def test_periodic_small_matches_oracle(torch, dtype, nint):
+    """Every (DM, frequency) image: the radix-2 time transform (32) and the
+    register/LDS one (64, 256)."""
+    p = rfgen.smallcase(nant=10, nint=nint, nchan=48, npix=128, seed=17)
     p.dms = np.array([0.0, 40.0])
     p.widths = [1]
     p.pulses = []
@@ -80,10 +82,10 @@ def test_periodic_small_matches_oracle(torch, dtype):
     vis = _train(p, 40.0, 8, 3, c + 5, c - 4, snr=25.0)
     host = vis if dtype == 0 else rfgen.to_cf16(vis)
     g = gpu_plan(p, vis_dtype=dtype)
-    say("periodic small, dtype", dtype)
+    say("periodic small, dtype", dtype, "nint", nint)
     rows = _compare(g, p, host, upload(vis, dtype))
-    assert (1, 4, c + 5, c - 4) in [(int(r["dm_idx"]), int(r["t_int"]), int(r["x"]), int(r["y"]))
-                                    for r in rows]
+    assert (1, nint // 8, c + 5, c - 4) in [(int(r["dm_idx"]), int(r["t_int"]), int(r["x"]),
+                                             int(r["y"])) for r in rows]
 
 
 def test_periodic_survey_transform(torch):
