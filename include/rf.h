@@ -469,7 +469,7 @@ rf_status rf_candidate_products(const rf_plan *plan, const void *d_vis, const rf
  * batch pipelines (streams) and `m_budget_mb` (16..4096) for the row-
  * transformed batches of all lanes together (image pairs per batch follow
  * from it).  Results do not depend on either (the same arithmetic per
- * image); speed does.  Defaults 2 and 240.  Changes
+ * image); speed does.  Defaults 2 and 240 (1920 for 2048^2 images).  Changes
  * rf_workspace_bytes(RF_OP_SEGMENT): call before sizing workspaces, and not
  * while the plan is in use.  RF_EINVAL on NULL, RF_ERANGE out of range. */
 rf_status rf_plan_set_tuning(rf_plan *plan, int32_t lanes, int32_t m_budget_mb);

@@ -19,6 +19,8 @@ from . import RF_OP_SEGMENT
 
 # (lanes, budget of all lanes' row-transformed batches in MB)
 CANDIDATES = [(1, 240), (2, 120), (2, 240), (2, 320), (3, 240), (4, 240)]
+# 2048^2 batches hold few image pairs at 240 MB: larger budgets are tried too
+LARGE_IMAGE_CANDIDATES = [(2, 960), (2, 1920), (3, 1920)]
 
 
 def shape_key(plan):
@@ -52,10 +54,14 @@ def _time(plan, vis, reps):
     return dt
 
 
-def tune(plan, vis, ndm=8, candidates=CANDIDATES, cache_path=None, reps=2):
+def tune(plan, vis, ndm=8, candidates=None, cache_path=None, reps=2):
     """Picks and applies the fastest schedule for `plan` (segment `vis` on the
     device).  Returns (lanes, m_budget_mb, info) with info["cached"] True when
-    the choice came from the cache, else the per-candidate seconds per DM."""
+    the choice came from the cache, else the per-candidate seconds per DM.
+    candidates: (lanes, budget MB) pairs; default CANDIDATES, plus
+    LARGE_IMAGE_CANDIDATES for 2048^2 images."""
+    if candidates is None:
+        candidates = CANDIDATES + (LARGE_IMAGE_CANDIDATES if plan.npix >= 2048 else [])
     key = f"{_device_name()}|{shape_key(plan)}"
     cache = _load(cache_path)
     if key in cache:

@@ -141,6 +141,11 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
   p->ndm = d->ndm;
   p->nwidth = d->nwidth;
   p->npix = N;
+  // default batch budget: 240 MB keeps the two lanes' row-transformed batches
+  // in the 256 MB last-level cache at 1024^2 and below; 2048^2 batches hold
+  // only a few image pairs at that size, and more pairs per batch pay more
+  // than the cache residency (measured: 1920 MB, 8% faster per DM trial)
+  p->m_budget_mb = N >= 2048 ? 1920 : 240;
   p->tint_s = d->tint_s;
   p->du = d->du;
   p->dv = d->dv;
