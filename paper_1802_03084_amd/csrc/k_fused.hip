@@ -149,7 +149,11 @@ __global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis
             } else {
               vi = make_float2(a0[j].x * iw, a0[j].y * iw);
             }
-            ws.out[j][(size_t)kout[j] * nbc + bc] = vi;
+            // each sample is read once, batches later: stream it past the caches
+            typedef float f2v __attribute__((ext_vector_type(2)));
+            const f2v x2 = {vi.x, vi.y};
+            __builtin_nontemporal_store(x2,
+                                        reinterpret_cast<f2v *>(&ws.out[j][(size_t)kout[j] * nbc + bc]));
             ++kout[j];
             a0[j] = make_float2(0.f, 0.f);
             a1[j] = a0[j];
