@@ -173,7 +173,9 @@ rf_status rf_dedisperse(const rf_plan *plan, int32_t dm_idx, const void *d_vis,
 /*
  * rf_resample (Figure 2 loop over sampling time): decimating boxcar mean
  *   d_out[k] = (sum_{j<width} d_in[k*width + j]) / width,  k < nin / width,
- * accumulated in float32 in increasing j.  d_in is [nin][nbl][nchan][npol]
+ * accumulated in float32 in increasing j and scaled by the float reciprocal
+ * of width (the quotient itself for powers of two; within one rounding of it
+ * otherwise), as the fused search does.  d_in is [nin][nbl][nchan][npol]
  * of the plan's vis_dtype; d_out is RF_CF32 [nin / width][nbl][nchan][npol].
  */
 rf_status rf_resample(const rf_plan *plan, int32_t width, const void *d_in, int32_t nin,
