@@ -398,11 +398,12 @@ def main():
     log2n = int(np.log2(N))
     in_bytes = dvis.numel() * dvis.element_size()
     vi_bytes = sum(p.nint // w for w in p.widths) * p.nbl * p.nchan * 8
-    algo = {  # algorithmic work per step and its unit
-        "drs": (len(p.dms) * (in_bytes + vi_bytes), "B"),
-        "grid": (plan.n_images * (p.nbl * p.nchan + plan.info["n_cells"]) * 8, "B"),
-        "rows": (pairs * n_rows * 5 * N * log2n, "flop"),
-        "cols": (pairs * N * 5 * N * log2n, "flop"),
+    # algorithmic work per step: (bytes that must cross HBM, flops)
+    algo = {
+        "drs": (len(p.dms) * (in_bytes + vi_bytes), 0),
+        "grid": (plan.n_images * (p.nbl * p.nchan + plan.info["n_cells"]) * 8, 0),
+        "rows": (pairs * (2 * plan.info["n_cells"] + n_rows * N) * 8, pairs * n_rows * 5 * N * log2n),
+        "cols": (pairs * n_rows * N * 8, pairs * N * 5 * N * log2n),
     }
     kernels = {k: {"ms_total": round(v[0], 2), "launches": v[1],
                    "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None}
@@ -418,35 +419,45 @@ def main():
     log("fused kernels (event-timed, serial): " + ", ".join(f"{k}={v:.2f} us" for k, v in serial.items()))
     dom = max((k for k in algo if k in kernels),
               key=lambda k: times_s[k][0] if times_s[k][1] else kernels[k]["ms_total"])
-    total_units, unit = algo[dom]
+    bytes_step, flops_step = algo[dom]
     launches = kernels[dom]["launches"]
     avg_s = kernels[dom]["ms_total"] * 1e-3 / launches
-    per_launch = total_units / launches
-    if unit == "B":
-        ach = per_launch / avg_s / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    b_launch, f_launch = bytes_step / launches, flops_step / launches
+    # The roofline that binds is the longer of the two lower bounds on the
+    # kernel's time (its algorithmic bytes at the HBM peak, its algorithmic
+    # flops at the fp32 vector peak): below the ridge point (peak flops / peak
+    # bandwidth) a kernel is HBM-bound.
+    hbm_bound = b_launch / (HBM_PEAK_GBS * 1e9) >= f_launch / (FP32_PEAK_TFLOPS * 1e12)
+    gbs = b_launch / avg_s / 1e9
+    tfs = f_launch / avg_s / 1e12
+    if hbm_bound:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
     else:
-        ach = per_launch / avg_s / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 2), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None}
-    roof.update({"avg_launch_us": round(avg_s * 1e6, 2), "alg_per_launch": per_launch,
-                 "launches": launches})
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(tfs, 2), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tfs / FP32_PEAK_TFLOPS, 4), "traffic": None}
+    roof.update({"avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": b_launch,
+                 "alg_flops_per_launch": f_launch, "launches": launches})
+    if f_launch:
+        roof["intensity_flop_per_B"] = round(f_launch / b_launch, 2)
+        roof["ridge_flop_per_B"] = round(FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9), 2)
+        roof["fp32"] = {"achieved_tflops": round(tfs, 2), "frac": round(tfs / FP32_PEAK_TFLOPS, 4)}
     if dom == "cols" and N == 1024 and cols_kernel_digest() == COLS_TRAFFIC["digest"]:
         t = COLS_TRAFFIC
         roof["traffic"] = round(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
         roof["traffic_unit"] = "B per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)"
     for k in algo:
         if k in kernels:
-            u, un = algo[k]
-            rate = u / (kernels[k]["ms_total"] * 1e-3)
-            kernels[k]["achieved"] = (f"{rate / 1e9:.0f} GB/s" if un == "B" else f"{rate / 1e12:.2f} TFLOP/s")
+            by, fl = algo[k]
+            sec = kernels[k]["ms_total"] * 1e-3
+            kernels[k]["achieved"] = f"{by / sec / 1e9:.0f} GB/s" + (
+                f", {fl / sec / 1e12:.2f} TFLOP/s" if fl else "")
 
     if dom in serial:
         s_avg = serial[dom] * 1e-6
-        ach_s = per_launch / s_avg / (1e9 if unit == "B" else 1e12)
-        roof["serial"] = {"avg_launch_us": serial[dom], "achieved": round(ach_s, 2),
-                          "frac": round(ach_s / roof["peak"], 4)}
+        per = b_launch / s_avg / 1e9 if hbm_bound else f_launch / s_avg / 1e12
+        roof["serial"] = {"avg_launch_us": serial[dom], "achieved": round(per, 2),
+                          "frac": round(per / roof["peak"], 4)}
 
     plain = None
     if not args.no_plain:
