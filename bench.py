@@ -203,6 +203,24 @@ def event_time(fn, reps, stream):
     return start.elapsed_time(end) / reps * 1e-3  # seconds per call
 
 
+def copy_rate(torch, nbytes, reps=5):
+    """Read + write GB/s of a plain device-to-device copy of nbytes."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    t1.synchronize()
+    dt = t0.elapsed_time(t1) / reps * 1e-3
+    del src, dst
+    return 2 * nbytes / dt / 1e9
+
+
 def large_leg(ndm, steps):
     """The large workload (351 baselines, 8192 x 1 ms, 1024 channels over
     2-4 GHz, widths 1..32, 2048^2 images) over ndm of its 400 DM trials spread
@@ -453,6 +471,24 @@ def main():
             kernels[k]["achieved"] = f"{by / sec / 1e9:.0f} GB/s" + (
                 f", {fl / sec / 1e12:.2f} TFLOP/s" if fl else "")
 
+    # per-stage HBM rates against the published peak and a measured plain
+    # device copy (read + write of 1 GiB)
+    copy_gbs = copy_rate(torch, 1 << 30)
+    stages = {}
+    for k in ("drs", "grid"):
+        if k in kernels:
+            by = algo[k][0]
+            for mode, sec in (("concurrent", kernels[k]["ms_total"] * 1e-3),
+                              ("serial", times_s[k][0] * 1e-3 if times_s[k][1] else None)):
+                if sec:
+                    r = by / sec / 1e9
+                    stages.setdefault(k, {})[mode] = {
+                        "GBps": round(r, 1), "frac_of_peak": round(r / HBM_PEAK_GBS, 4),
+                        "frac_of_copy": round(r / copy_gbs, 4)}
+    log(f"copy {copy_gbs:.0f} GB/s; stages: " + ", ".join(
+        f"{k} {v['serial']['GBps']:.0f} GB/s serial ({100 * v['serial']['frac_of_peak']:.0f}% of peak)"
+        for k, v in stages.items() if "serial" in v))
+
     if dom in serial:
         s_avg = serial[dom] * 1e-6
         per = b_launch / s_avg / 1e9 if hbm_bound else f_launch / s_avg / 1e12
@@ -528,6 +564,7 @@ def main():
         "kernels": kernels,
         "kernels_serial_avg_us": serial,
         "roofline": roof,
+        "hbm_stages": {"copy_GBps": round(copy_gbs, 1), "peak_GBps": HBM_PEAK_GBS, **stages},
         "cpu_baseline": cpu,
         "serving": serving,
         "periodic": periodic,
