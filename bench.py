@@ -389,6 +389,10 @@ def main():
         rows, n, _ = plan.search_segment(dvis, cap=cap, ws=ws)
         log(f"warmup {w}: {time.perf_counter() - t:.2f}s, {n} candidates")
 
+    # The timed steps: the fused search alone, in its own schedule (two lane
+    # streams).  No events are recorded in them: an event on a launch (a
+    # marker, or one attached to the dispatch) changes how the lanes overlap,
+    # and with events on every launch a step takes about a fifth longer.
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -404,12 +408,7 @@ def main():
     log(f"{img_s:.0f} images/s, {step_s * 1e3:.1f} ms/step, RTF {seg_s / step_s:.2f}, "
         f"pulses recovered {found}/{len(p.pulses)}, candidates {n}")
 
-    # Event-timed kernels: one more step in the timed configuration (the same
-    # lane streams), with an event pair on each launch's own stream.  Kernels
-    # of the two lanes run concurrently, so a kernel's duration includes the
-    # time it shares the device; the serial figures are from --profile-only.
     N = p.npix
-    times, _, _ = plan.profile_segment(dvis, cap=cap, ws=ws, concurrent=True)
     nw = len(p.widths)
     n_rows = plan.info["n_rows"]
     pairs = len(p.dms) * sum((p.nint // w + 1) // 2 for w in p.widths)
@@ -423,23 +422,21 @@ def main():
         "rows": (pairs * (2 * plan.info["n_cells"] + n_rows * N) * 8, pairs * n_rows * 5 * N * log2n),
         "cols": (pairs * n_rows * N * 8, pairs * N * 5 * N * log2n),
     }
-    kernels = {k: {"ms_total": round(v[0], 2), "launches": v[1],
-                   "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None}
-               for k, v in times.items() if v[1]}
-    log("fused kernels (event-timed step, lanes concurrent): " +
-        ", ".join(f"{k}={v['ms_total']:.1f} ms/{v['launches']}" for k, v in kernels.items()))
-    # The same kernels with every launch in order on one stream (durations do
-    # not overlap): each kernel's standalone rate.  The dominant kernel is the
-    # one with the most serial time per step (concurrent durations share the
-    # device and fluctuate).
+    # Kernel durations: one more search with every launch in order on one
+    # stream, an event pair attached to each dispatch (the launches do not
+    # overlap, so the events change no overlap): each kernel's standalone rate,
+    # the basis of its roofline.  Sharing the device, the two lanes' kernels
+    # each take longer (the rocprofv3 trace of the timed steps shows it).
     times_s, _, _ = plan.profile_segment(dvis, cap=cap, ws=ws, concurrent=False)
-    serial = {k: round(1e3 * v[0] / v[1], 2) for k, v in times_s.items() if v[1]}
-    log("fused kernels (event-timed, serial): " + ", ".join(f"{k}={v:.2f} us" for k, v in serial.items()))
-    dom = max((k for k in algo if k in kernels),
-              key=lambda k: times_s[k][0] if times_s[k][1] else kernels[k]["ms_total"])
+    kernels = {k: {"launches_per_step": v[1], "avg_us": round(1e3 * v[0] / v[1], 2)}
+               for k, v in times_s.items() if v[1]}
+    log("fused kernels (event-timed, serial): " +
+        ", ".join(f"{k}={v['avg_us']:.2f} us x{v['launches_per_step']}" for k, v in kernels.items()))
+    dom = max((k for k in algo if k in kernels), key=lambda k: times_s[k][0])
+    per_step = {k: times_s[k][1] for k in times_s if times_s[k][1]}
     bytes_step, flops_step = algo[dom]
-    launches = kernels[dom]["launches"]
-    avg_s = kernels[dom]["ms_total"] * 1e-3 / launches
+    launches = per_step[dom]
+    avg_s = kernels[dom]["avg_us"] * 1e-6
     b_launch, f_launch = bytes_step / launches, flops_step / launches
     # The roofline that binds is the longer of the two lower bounds on the
     # kernel's time (its algorithmic bytes at the HBM peak, its algorithmic
@@ -455,7 +452,10 @@ def main():
         roof = {"bound": "alu", "kernel": dom, "achieved": round(tfs, 2), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(tfs / FP32_PEAK_TFLOPS, 4), "traffic": None}
     roof.update({"avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": b_launch,
-                 "alg_flops_per_launch": f_launch, "launches": launches})
+                 "alg_flops_per_launch": f_launch, "launches_per_step": launches,
+                 "timing": "HIP start/stop events attached to each dispatch (hipExtLaunchKernel) "
+                           "on the launch's stream, one search with the launches in order on one "
+                           "stream (the kernel alone on the device)"})
     if f_launch:
         roof["intensity_flop_per_B"] = round(f_launch / b_launch, 2)
         roof["ridge_flop_per_B"] = round(FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9), 2)
@@ -465,9 +465,9 @@ def main():
         roof["traffic"] = round(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
         roof["traffic_unit"] = "B per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)"
     for k in algo:
-        if k in kernels:
+        if k in kernels and k in per_step:
             by, fl = algo[k]
-            sec = kernels[k]["ms_total"] * 1e-3
+            sec = kernels[k]["avg_us"] * 1e-6 * per_step[k]  # kernel time per step
             kernels[k]["achieved"] = f"{by / sec / 1e9:.0f} GB/s" + (
                 f", {fl / sec / 1e12:.2f} TFLOP/s" if fl else "")
 
@@ -478,8 +478,7 @@ def main():
     for k in ("drs", "grid"):
         if k in kernels:
             by = algo[k][0]
-            for mode, sec in (("concurrent", kernels[k]["ms_total"] * 1e-3),
-                              ("serial", times_s[k][0] * 1e-3 if times_s[k][1] else None)):
+            for mode, sec in (("serial", times_s[k][0] * 1e-3 if times_s[k][1] else None),):
                 if sec:
                     r = by / sec / 1e9
                     stages.setdefault(k, {})[mode] = {
@@ -488,12 +487,6 @@ def main():
     log(f"copy {copy_gbs:.0f} GB/s; stages: " + ", ".join(
         f"{k} {v['serial']['GBps']:.0f} GB/s serial ({100 * v['serial']['frac_of_peak']:.0f}% of peak)"
         for k, v in stages.items() if "serial" in v))
-
-    if dom in serial:
-        s_avg = serial[dom] * 1e-6
-        per = b_launch / s_avg / 1e9 if hbm_bound else f_launch / s_avg / 1e12
-        roof["serial"] = {"avg_launch_us": serial[dom], "achieved": round(per, 2),
-                          "frac": round(per / roof["peak"], 4)}
 
     plain = None
     if not args.no_plain:
@@ -562,7 +555,6 @@ def main():
         "pulses_recovered": f"{found}/{len(p.pulses)}",
         "candidates": n,
         "kernels": kernels,
-        "kernels_serial_avg_us": serial,
         "roofline": roof,
         "hbm_stages": {"copy_GBps": round(copy_gbs, 1), "peak_GBps": HBM_PEAK_GBS, **stages},
         "cpu_baseline": cpu,

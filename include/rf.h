@@ -250,18 +250,24 @@ typedef struct rf_kernel_times {
                               of rf_search_segment (concurrent batches: one
                               kernel's duration includes the time it shares the
                               device with the other streams' kernels)          */
-  int32_t reserved;        /* in: 0                                             */
+  int32_t sample;          /* in: time every sample-th launch of each kind (the
+                              first included); 0 or 1 = every launch.  Events
+                              around every launch delay the next launch on the
+                              stream and change how the streams overlap; a
+                              sparse sample keeps the schedule of
+                              rf_search_segment                                */
   double ms[RF_NK];        /* out: summed event-timed duration, milliseconds   */
   int64_t launches[RF_NK]; /* out: number of launches timed                    */
 } rf_kernel_times;
 
 /*
  * rf_search_segment_profile: rf_search_segment with an event pair recorded
- * around every kernel launch; ms and launches of *times receive the summed
- * durations per kernel kind (concurrent and reserved are read, then kept).
- * Results are identical to rf_search_segment; the extra events and a
- * synchronisation every few thousand launches make it slower, so time
- * throughput with rf_search_segment.  RF_EINVAL if concurrent is not 0 or 1.
+ * around the sampled kernel launches; ms and launches of *times receive the
+ * summed durations per kernel kind (concurrent and sample are read, then
+ * kept).  Results are identical to rf_search_segment; with every launch timed
+ * the extra events (and a synchronisation every 16384 launches timed) make it
+ * slower, so time throughput with rf_search_segment or a sparse sample.
+ * RF_EINVAL if concurrent is not 0 or 1, RF_ERANGE if sample < 0.
  */
 rf_status rf_search_segment_profile(const rf_plan *plan, const void *d_vis, rf_candidate *d_cand,
                                     int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,

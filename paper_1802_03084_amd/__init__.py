@@ -360,11 +360,12 @@ class Plan:
                    "rf_search_periodic")
         return self._collect(cand, ncand, stats, cap)
 
-    def profile_segment(self, vis, cap=65536, ws=None, stream=None, concurrent=False):
-        """rf_search_segment_profile: one fused search with every kernel launch
-        event-timed.  concurrent=False runs every launch in order on one stream
-        (durations do not overlap); True runs the streams of search_segment.
-        Returns ({kind: (ms_total, launches)}, candidates, count)."""
+    def profile_segment(self, vis, cap=65536, ws=None, stream=None, concurrent=False, sample=1):
+        """rf_search_segment_profile: one fused search with kernel launches
+        event-timed (every sample-th launch of each kind).  concurrent=False
+        runs every launch in order on one stream (durations do not overlap);
+        True runs the streams of search_segment.
+        Returns ({kind: (ms_total, launches timed)}, candidates, count)."""
         torch = _torch()
         self._check_vis(vis, self.nint)
         if ws is None:
@@ -373,6 +374,7 @@ class Plan:
         ncand = torch.zeros(1, dtype=torch.int32, device=self.device)
         kt = _lib.KernelTimes()
         kt.concurrent = 1 if concurrent else 0
+        kt.sample = int(sample)
         _lib.check(_lib.load().rf_search_segment_profile(self._h, _ptr(vis), _ptr(cand), int(cap), _ptr(ncand),
                                                          None, _ptr(ws), ws.numel(), _stream(stream),
                                                          ctypes.byref(kt)), "rf_search_segment_profile")

@@ -67,7 +67,7 @@ class Candidate(ctypes.Structure):
 
 
 class KernelTimes(ctypes.Structure):
-    _fields_ = [("concurrent", c_i32), ("reserved", c_i32), ("ms", ctypes.c_double * 8),
+    _fields_ = [("concurrent", c_i32), ("sample", c_i32), ("ms", ctypes.c_double * 8),
                 ("launches", c_i64 * 8)]
 
 

@@ -22,6 +22,7 @@
 #include "rf_internal.h"
 #include "fft.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
@@ -955,12 +956,22 @@ Layout layout_of(const rf_plan *p) {
 // the recorded events (on every stream given to sync()) and sums the pairs.
 struct Timer {
   rf_kernel_times *kt = nullptr;
+  int sample = 1;  // time every sample-th launch of each kind (the first included)
+  int64_t seen[RF_NK] = {};
+  bool open = false;  // the launch between the current mark pair is timed
   std::vector<hipStream_t> streams;  // every stream that records events
   std::vector<hipEvent_t> pool;
   std::vector<int> kind;
   size_t used = 0;
   hipError_t mark(int k, hipStream_t s) {  // before (k >= 0) and after (k = -1) a launch
     if (!kt) return hipSuccess;
+    if (k >= 0) {
+      open = seen[k]++ % sample == 0;
+      if (!open) return hipSuccess;
+    } else {
+      if (!open) return hipSuccess;
+      open = false;
+    }
     if (used == pool.size()) {
       hipEvent_t e;
       const hipError_t err = hipEventCreate(&e);
@@ -970,7 +981,31 @@ struct Timer {
     if (k >= 0) kind.push_back(k);
     return hipEventRecord(pool[used++], s);
   }
-  bool full() const { return used >= 8192; }
+  // Launches kernel k of `kind` on s.  A sampled launch carries a start and a
+  // stop event recorded by the dispatch itself (hipExtLaunchKernel): no
+  // packets are added to the stream around it, so the schedule is the
+  // untimed one and the duration is the kernel's own.
+  template <typename... KArgs, typename... Args>
+  hipError_t launch(int k, void (*kern)(KArgs...), dim3 grid, dim3 block, hipStream_t s,
+                    Args... args) {
+    static_assert(sizeof...(KArgs) == sizeof...(Args), "kernel argument count");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (kt && seen[k]++ % sample == 0) {
+      while (pool.size() < used + 2) {
+        hipEvent_t e;
+        const hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        pool.push_back(e);
+      }
+      e0 = pool[used];
+      e1 = pool[used + 1];
+      used += 2;
+      kind.push_back(k);
+    }
+    hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0u, static_cast<KArgs>(args)...);
+    return hipGetLastError();
+  }
+  bool full() const { return used >= 32768; }
   hipError_t flush() {
     if (!kt || used == 0) return hipSuccess;
     for (hipStream_t s : streams) {
@@ -992,13 +1027,6 @@ struct Timer {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
 };
-#define RF_TIMED(tm, k, s, launch)       \
-  do {                                   \
-    RF_HIP_TRY((tm)->mark(k, s));        \
-    launch;                              \
-    RF_HIP_TRY(hipGetLastError());       \
-    RF_HIP_TRY((tm)->mark(-1, s));       \
-  } while (0)
 
 // Streams and events of a segment search: lane streams, a stream for the
 // per-DM pass over the segment, and the events ordering them; default
@@ -1059,26 +1087,22 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
   const int ngrp = (nimg_b + kCellImgs - 1) / kCellImgs;
   const int rep = ngrp >= 8 ? 1 : 8 / ngrp;
   const int per_xcd = rep == 1 ? (ngrp + 7) / 8 * p->n_cblk : (p->n_cblk + rep - 1) / rep;
-  RF_TIMED(tm, RF_K_GRID, s,
-           (k_cellsum<<<(unsigned)(8 * per_xcd), kCellThreads, 0, s>>>(
-               vi, p->nbl * p->nchan, 2 * p0, nimg_b, p->n_cells, p->n_cblk, p->d_cblk,
-               p->d_ucell_off, p->d_contrib, cv, rep)));
-  RF_TIMED(tm, RF_K_ROWS, s,
-           (k_rows_pairs<N><<<(unsigned)(npb * p->n_rp), RowPairCfg<N>::NT, 0, s>>>(
-               cv, p->n_cells, nimg_w, p0, pbn, p->d_rp_row, p->d_rp_sa, p->d_rp_sb, p->n_rp,
-               p->n_rows, p->d_zs_off, p->d_zs_u, p->d_zs_ck, p->d_zs_cmk, half_inv_w(p),
-               p->d_tw, M, epart)));
+  RF_HIP_TRY(tm->launch(RF_K_GRID, k_cellsum, dim3(8 * per_xcd), dim3(kCellThreads), s, vi,
+                        p->nbl * p->nchan, 2 * p0, nimg_b, p->n_cells, p->n_cblk, p->d_cblk,
+                        p->d_ucell_off, p->d_contrib, cv, rep));
+  RF_HIP_TRY(tm->launch(RF_K_ROWS, k_rows_pairs<N>, dim3(npb * p->n_rp), dim3(RowPairCfg<N>::NT),
+                        s, cv, p->n_cells, nimg_w, p0, pbn, p->d_rp_row, p->d_rp_sa, p->d_rp_sb,
+                        p->n_rp, p->n_rows, p->d_zs_off, p->d_zs_u, p->d_zs_ck, p->d_zs_cmk,
+                        half_inv_w(p), p->d_tw, M, epart));
   const float inv_w = 1.0f / (float)p->W;
   const int cgrid = (pbn * sh.cbp + 7) / 8 * 8;
-  RF_TIMED(tm, RF_K_COLS, s,
-           (k_cols_stats<N><<<(unsigned)cgrid, ColCfg<N>::NT, 0, s>>>(
-               M, p->n_rows, p->vmax, nimg_w, p0, pbn, inv_w, p->d_tw, epart, p->n_rp,
-               part, list, sh.capb)));
-  RF_TIMED(tm, RF_K_SELECT, s,
-           (k_select<<<(unsigned)(2 * pbn), kSelThreads, 0, s>>>(
-               part, list, sh.cbp, sh.capb, nimg_w, p0, pbn, N, dm_idx, width_idx, width,
-               stat_base, stats, cand, cap, ncand, fb, fb + 1, p->threshold, p->t_begin,
-               p->t_end)));
+  RF_HIP_TRY(tm->launch(RF_K_COLS, k_cols_stats<N>, dim3(cgrid), dim3(ColCfg<N>::NT), s, M,
+                        p->n_rows, p->vmax, nimg_w, p0, pbn, inv_w, p->d_tw, epart, p->n_rp, part,
+                        list, sh.capb));
+  RF_HIP_TRY(tm->launch(RF_K_SELECT, k_select, dim3(2 * pbn), dim3(kSelThreads), s, part, list,
+                        sh.cbp, sh.capb, nimg_w, p0, pbn, N, dm_idx, width_idx, width, stat_base,
+                        stats, cand, cap, ncand, fb, fb + 1, p->threshold, p->t_begin,
+                        p->t_end));
   return RF_OK;
 }
 
@@ -1126,24 +1150,22 @@ rf_status drs_timed(const rf_plan *p, const int32_t *d_delay_row, const void *vi
     ws.nw = n;
     const int tchunk = L * std::max(1, 64 / L);
     dim3 grid((nbc + kDrsThreads - 1) / kDrsThreads, (p->nint + tchunk - 1) / tchunk);
-    RF_HIP_TRY(tm->mark(RF_K_DRS, s));
+    const dim3 blk(kDrsThreads);
     if (p->vis_dtype == RF_CF32) {
       if (p->npol == 2)
-        k_drs<float2, 2><<<grid, kDrsThreads, 0, s>>>((const float2 *)vis, d_delay_row, p->nint,
-                                                      nbc, p->nchan, tchunk, ws);
+        RF_HIP_TRY(tm->launch(RF_K_DRS, k_drs<float2, 2>, grid, blk, s, (const float2 *)vis,
+                              d_delay_row, p->nint, nbc, p->nchan, tchunk, ws));
       else
-        k_drs<float2, 1><<<grid, kDrsThreads, 0, s>>>((const float2 *)vis, d_delay_row, p->nint,
-                                                      nbc, p->nchan, tchunk, ws);
+        RF_HIP_TRY(tm->launch(RF_K_DRS, k_drs<float2, 1>, grid, blk, s, (const float2 *)vis,
+                              d_delay_row, p->nint, nbc, p->nchan, tchunk, ws));
     } else {
       if (p->npol == 2)
-        k_drs<__half2, 2><<<grid, kDrsThreads, 0, s>>>((const __half2 *)vis, d_delay_row,
-                                                       p->nint, nbc, p->nchan, tchunk, ws);
+        RF_HIP_TRY(tm->launch(RF_K_DRS, k_drs<__half2, 2>, grid, blk, s, (const __half2 *)vis,
+                              d_delay_row, p->nint, nbc, p->nchan, tchunk, ws));
       else
-        k_drs<__half2, 1><<<grid, kDrsThreads, 0, s>>>((const __half2 *)vis, d_delay_row,
-                                                       p->nint, nbc, p->nchan, tchunk, ws);
+        RF_HIP_TRY(tm->launch(RF_K_DRS, k_drs<__half2, 1>, grid, blk, s, (const __half2 *)vis,
+                              d_delay_row, p->nint, nbc, p->nchan, tchunk, ws));
     }
-    RF_HIP_TRY(hipGetLastError());
-    RF_HIP_TRY(tm->mark(-1, s));
     j += n;
   }
   return RF_OK;
@@ -1310,6 +1332,7 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
                       hipStream_t s, rf_kernel_times *kt) {
   Timer timer;
   timer.kt = kt;
+  if (kt) timer.sample = std::max(1, kt->sample);
   timer.streams.push_back(s);
   char *ws = static_cast<char *>(ws_v);
   int32_t *fb = (int32_t *)(ws + layout_of(p).fb);

@@ -633,10 +633,11 @@ rf_status rf_search_segment_profile(const rf_plan *p, const void *d_vis, rf_cand
   if (ws_bytes < need) return RF_EWORKSPACE;
   if (!d_ws) return RF_EINVAL;
   if (times->concurrent != 0 && times->concurrent != 1) return RF_EINVAL;
-  const int32_t conc = times->concurrent, res = times->reserved;
+  if (times->sample < 0) return RF_ERANGE;
+  const int32_t conc = times->concurrent, smp = times->sample;
   std::memset(times, 0, sizeof(*times));
   times->concurrent = conc;
-  times->reserved = res;
+  times->sample = smp;
   return run_segment(p, d_vis, d_cand, cap, d_ncand, d_stats, d_ws, ws_bytes,
                      (hipStream_t)stream, times);
 }
