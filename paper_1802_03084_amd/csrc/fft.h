@@ -413,10 +413,13 @@ struct RowCfg {  // dense rows: F grid rows per workgroup
   static constexpr int STRIDE = RowFft<N>::PADDED;
 };
 template <int N>
-struct ColCfg {  // columns: COLS columns per workgroup (~70 KB LDS: two workgroups per CU)
-  static constexpr int COLS = N >= 2048 ? 4 : (N >= 1024 ? 8 : (N >= 512 ? 16 : 32 < N ? 32 : N));
+struct ColCfg {  // columns: COLS columns per workgroup
+  // 4 columns from 1024 up (~35 KB LDS at 1024: four workgroups per CU,
+  // whose load and transform phases interleave; ~70 KB at 2048), else 8192
+  // points per workgroup
+  static constexpr int COLS = N >= 1024 ? 4 : (N >= 512 ? 16 : 32 < N ? 32 : N);
   static constexpr int FIRST = COLS * N / ColFft<N>::R0;  // first-pass butterflies
-  static constexpr int NT = N >= 512 ? 512 : (FIRST < 256 ? 256 : FIRST);
+  static constexpr int NT = N >= 512 ? (FIRST < 512 ? FIRST : 512) : (FIRST < 256 ? 256 : FIRST);
   // Columns vary fastest across lanes: a 64-bit LDS access serves 16 lanes
   // per cycle (COLS columns x 16/COLS butterflies), whose slots f STRIDE +
   // 17 j + r (first pass; the other passes alike) fall on distinct 8-byte

@@ -268,7 +268,9 @@ __global__ __launch_bounds__(kCellThreads) void k_cellsum(
 // pass.
 template <int N>
 struct RowPairCfg {
-  static constexpr int PBW = N >= 2048 ? 2 : 4;  // image pairs per workgroup (~68 KB LDS)
+  // image pairs per workgroup: from 1024 up two (~35 KB LDS at 1024, four
+  // workgroups per CU, so that their load and transform phases interleave)
+  static constexpr int PBW = N >= 1024 ? 2 : 4;
   static constexpr int F = 2 * PBW;              // transforms per workgroup
   static constexpr int NT = F * N / RowFft<N>::R0 < 256 ? 256 : F * N / RowFft<N>::R0;
   static constexpr int STRIDE = RowFft<N>::PADDED;
@@ -620,12 +622,12 @@ __device__ __forceinline__ void sel_bin(const uint32_t *hist, uint32_t rank, uin
 
 constexpr int kMaxCB = 512;       // column workgroups per image, at most
 constexpr int kLdsVals = 20480;   // bracket values staged in LDS (80 KB)
-constexpr int kLoadGroup = 8;     // list regions a wave loads at once
 
 // Per image: combines the column workgroups' records (peak, count below the
 // bracket, bracket counts), stages every kept bracket value in LDS, and finds
 // the median |value| among them.  Images whose median is not inside the
 // bracket, or whose bracket values did not all fit, go to the exact fallback.
+template <int VPR>  // values of each list region loaded up front (64 or 128)
 __global__ __launch_bounds__(kSelThreads) void k_select(
     const ColPart *__restrict__ part, const float *__restrict__ list, int cbn, int capb,
     int nimg_w, int p0, int pbn, int npix, int dm_idx,
@@ -741,27 +743,29 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
     med = 0.f;  // identically zero image (every pixel equals the zero peak)
   } else if (!ovf && s_lo <= rank && rank < s_lo + n) {
     uint32_t r = rank - s_lo;
-    // stage the regions in LDS: a wave takes kLoadGroup regions at a time with
-    // their first 128 values' loads all in flight (regions hold ~70 values)
+    // stage the regions in LDS: a wave takes G regions at a time with their
+    // first VPR values' loads all in flight (16 loads per lane; VPR is chosen
+    // above a region's typical count)
     const float *lr = list + (size_t)il * cbn * capb;
-    constexpr int NWV = kSelThreads / 64;
-    for (int g0 = wid; g0 < cbn; g0 += NWV * kLoadGroup) {
-      float x0[kLoadGroup], x1[kLoadGroup];
+    constexpr int NWV = kSelThreads / 64, PR = VPR / 64, G = 16 / PR;
+    for (int g0 = wid; g0 < cbn; g0 += NWV * G) {
+      float x[G][PR];
 #pragma unroll
-      for (int u = 0; u < kLoadGroup; ++u) {
+      for (int u = 0; u < G; ++u) {
         const int rg = min(g0 + u * NWV, cbn - 1);
         const float *rp = lr + (size_t)rg * capb;
-        x0[u] = rp[lane];
-        x1[u] = rp[lane + 64];
+#pragma unroll
+        for (int h = 0; h < PR; ++h) x[u][h] = rp[lane + 64 * h];
       }
 #pragma unroll
-      for (int u = 0; u < kLoadGroup; ++u) {
+      for (int u = 0; u < G; ++u) {
         const int rg = g0 + u * NWV;
         if (rg < cbn) {
           const uint32_t c = r_cnt[rg], o = r_off[rg];
-          if ((uint32_t)lane < c) vals[o + lane] = x0[u];
-          if ((uint32_t)lane + 64 < c) vals[o + lane + 64] = x1[u];
-          for (uint32_t e = lane + 128; e < c; e += 64) vals[o + e] = lr[(size_t)rg * capb + e];
+#pragma unroll
+          for (int h = 0; h < PR; ++h)
+            if ((uint32_t)(lane + 64 * h) < c) vals[o + lane + 64 * h] = x[u][h];
+          for (uint32_t e = lane + VPR; e < c; e += 64) vals[o + e] = lr[(size_t)rg * capb + e];
         }
       }
     }
@@ -1099,7 +1103,10 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
   RF_HIP_TRY(tm->launch(RF_K_COLS, k_cols_stats<N>, dim3(cgrid), dim3(ColCfg<N>::NT), s, M,
                         p->n_rows, p->vmax, nimg_w, p0, pbn, inv_w, p->d_tw, epart, p->n_rp, part,
                         list, sh.capb));
-  RF_HIP_TRY(tm->launch(RF_K_SELECT, k_select, dim3(2 * pbn), dim3(kSelThreads), s, part, list,
+  // a list region holds about COLS N x 0.86% x (bracket half-width in %) values
+  constexpr int per_region = (int)(ColCfg<N>::COLS * N * 0.86f * bracket_of<N>());
+  RF_HIP_TRY(tm->launch(RF_K_SELECT, k_select<(per_region > 48 ? 128 : 64)>, dim3(2 * pbn),
+                        dim3(kSelThreads), s, part, list,
                         sh.cbp, sh.capb, nimg_w, p0, pbn, N, dm_idx, width_idx, width, stat_base,
                         stats, cand, cap, ncand, fb, fb + 1, p->threshold, p->t_begin,
                         p->t_end));
