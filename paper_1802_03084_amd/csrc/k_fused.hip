@@ -268,9 +268,9 @@ __global__ __launch_bounds__(kCellThreads) void k_cellsum(
 // pass.
 template <int N>
 struct RowPairCfg {
-  // image pairs per workgroup: from 1024 up two (~35 KB LDS at 1024, four
-  // workgroups per CU, so that their load and transform phases interleave)
-  static constexpr int PBW = N >= 1024 ? 2 : 4;
+  // image pairs per workgroup: ~35 KB of LDS from 1024 up (four workgroups
+  // per CU, so that their load and transform phases interleave)
+  static constexpr int PBW = N >= 2048 ? 1 : (N >= 1024 ? 2 : 4);
   static constexpr int F = 2 * PBW;              // transforms per workgroup
   static constexpr int NT = F * N / RowFft<N>::R0 < 256 ? 256 : F * N / RowFft<N>::R0;
   static constexpr int STRIDE = RowFft<N>::PADDED;
