@@ -140,8 +140,8 @@ struct FftShape {
 };
 
 // Row transforms (along u) and column transforms (along v).  From 512 up the
-// passes are of radix up to 16, so that a thread of a 512-thread workgroup
-// holds 16 values and four waves per SIMD fit in the register file.
+// passes are of radix up to 16, so that a thread holds at most 16 values and
+// four waves per SIMD fit in the register file.
 template <int N> struct RowFft;
 template <> struct RowFft<64> : FftShape<64, 8, 8, 1> {};
 template <> struct RowFft<128> : FftShape<128, 16, 8, 1> {};
