@@ -268,9 +268,10 @@ __global__ __launch_bounds__(kCellThreads) void k_cellsum(
 // pass.
 template <int N>
 struct RowPairCfg {
-  // image pairs per workgroup: ~35 KB of LDS from 1024 up (four workgroups
-  // per CU, so that their load and transform phases interleave)
-  static constexpr int PBW = N >= 2048 ? 1 : (N >= 1024 ? 2 : 4);
+  // image pairs per workgroup: ~35 KB of LDS from 1024 up, ~18 KB at 512
+  // (256 threads), so that several workgroups per CU interleave their load
+  // and transform phases
+  static constexpr int PBW = N >= 2048 ? 1 : (N >= 512 ? 2 : 4);
   static constexpr int F = 2 * PBW;              // transforms per workgroup
   static constexpr int NT = F * N / RowFft<N>::R0 < 256 ? 256 : F * N / RowFft<N>::R0;
   static constexpr int STRIDE = RowFft<N>::PADDED;
