@@ -42,7 +42,7 @@ constexpr float kMedOverRms = 0.6745f; // median |x| / rms of a zero-mean Gaussi
 template <int N>
 constexpr float bracket_of() { return N >= 2048 ? 0.004f : 0.01f; }
 constexpr int kDrsThreads = 256;
-constexpr int kSelThreads = 256;
+constexpr int kSelThreads = 512;
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
 constexpr int kBins = 2048;
 constexpr uint32_t kBinCap = 1024;  // values of one bracket bin ranked directly
 
-__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t *wsum) {
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *wsum) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint32_t inc = x;
 #pragma unroll
@@ -597,22 +597,25 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t *wsu
   return inc - x + add;
 }
 
-// Finds the bin of hist[kBins] that holds `rank`; 8 bins per thread.
+// Finds the bin of hist[kBins] that holds `rank`; BPT consecutive bins per
+// thread.
 __device__ __forceinline__ void sel_bin(const uint32_t *hist, uint32_t rank, uint32_t *wsum,
                                         uint32_t *sel) {
+  constexpr int BPT = kBins / kSelThreads;
+  static_assert(BPT * kSelThreads == kBins, "bins divide over the threads");
   const int t = threadIdx.x;
-  uint32_t h[8], tot = 0;
+  uint32_t h[BPT], tot = 0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    h[i] = hist[8 * t + i];
+  for (int i = 0; i < BPT; ++i) {
+    h[i] = hist[BPT * t + i];
     tot += h[i];
   }
-  uint32_t pre = block_excl_scan256(tot, wsum);
+  uint32_t pre = block_excl_scan(tot, wsum);
   if (rank >= pre && rank < pre + tot) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < BPT; ++i) {
       if (rank >= pre && rank < pre + h[i]) {
-        sel[0] = 8 * t + i;
+        sel[0] = BPT * t + i;
         sel[1] = rank - pre;
       }
       pre += h[i];
@@ -660,7 +663,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
   const ColPart *pp = part + (size_t)il * cbn;
   {  // combine the column workgroups' records; region r holds r_cnt[r] values
      // placed at r_off[r] in LDS (kMaxCB / kSelThreads consecutive regions per thread)
-    constexpr int RPT = kMaxCB / kSelThreads;
+    constexpr int RPT = kMaxCB > kSelThreads ? kMaxCB / kSelThreads : 1;
     float v = -__builtin_inff();
     int32_t i = 0x7fffffff;
     uint32_t lo = 0, nn = 0, of = 0, cnt[RPT];
