@@ -349,17 +349,6 @@ __device__ __forceinline__ void fft_rest_blocks(float2 *buf, const float2 *__res
   }
 }
 
-// The last pass of fft_rest_blocks once more (buf still holds its input: the
-// last pass only reads it), handing the same butterflies to consume.
-template <class Sh, int F, int NT, int S, bool JF, bool PRE, class Consume>
-__device__ __forceinline__ void fft_last_again(const float2 *buf, const float2 *__restrict__ tw,
-                                               int tid, Consume consume) {
-  if constexpr (Sh::R2 == 1)
-    fft_last_block<Sh, Sh::R1, Sh::R0, F, NT, S, JF, !PRE>(buf, tw, tid, consume);
-  else
-    fft_last_block<Sh, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF, true>(buf, tw, tid, consume);
-}
-
 // Inverse (exp(+i)) unnormalised FFT of F sequences of length N: inputs from
 // load(f, i), outputs to store(f, k, value), LDS buf of F * S elements
 // (S >= Sh::PADDED) for the exchanges between passes.

@@ -444,6 +444,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
   const auto rla = buf_rsrc(list + ((size_t)(2 * pl) * CB + cb) * capb, (uint32_t)capb * 4u);
   const auto rlb = buf_rsrc(list + ((size_t)(2 * pl + 1) * CB + cb) * capb, (uint32_t)capb * 4u);
   float bva = -__builtin_inff(), bvb = -__builtin_inff();
+  int bia = 0x7fffffff, bib = 0x7fffffff;
   uint32_t ca = 0, cbn = 0;
   fft_rest_blocks<Sh, COLS, NT, S, false, true>(buf, tw, tid, [&](int f, int k0, int ks, auto &v) {
     constexpr int R = sizeof(v) / sizeof(v[0]);
@@ -451,16 +452,38 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
     // are then never used (no record is written for it and no select reads
     // its list region), and the loop stays free of branches.
     //
-    // Only the peak value is tracked here; its lowest index is found after
-    // the tile's maximum is known (below).  The outputs are already image
-    // pixels: 1/W is folded into Z.
+    // The peak: the butterfly's maximum and the lowest of its outputs that
+    // hold it (the outputs ascend in flat index with r), merged into the
+    // thread's peak by value, then lower flat index.  The outputs are
+    // already image pixels: 1/W is folded into Z.
+    {
+      float ma = v[0].x, mb = v[0].y;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        ma = fmaxf(ma, v[r].x);
+        mb = fmaxf(mb, v[r].y);
+      }
+      int ra = R - 1, rb = R - 1;
+#pragma unroll
+      for (int r = R - 2; r >= 0; --r) {
+        ra = v[r].x == ma ? r : ra;
+        rb = v[r].y == mb ? r : rb;
+      }
+      const int ia = (k0 + ra * ks) * N + x0 + f, ib = (k0 + rb * ks) * N + x0 + f;
+      if (better(ma, ia, bva, bia)) {
+        bva = ma;
+        bia = ia;
+      }
+      if (better(mb, ib, bvb, bib)) {
+        bvb = mb;
+        bib = ib;
+      }
+    }
     float aa[R], ab[R];
     uint64_t ba[R], bb[R];  // wave masks of bracket members, per output row
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const float pa = v[r].x, pb = v[r].y;
-      bva = fmaxf(bva, pa);
-      bvb = fmaxf(bvb, pb);
       aa[r] = fabsf(pa);
       ab[r] = fabsf(pb);
       // wave-uniform count below the bracket; members by one unsigned compare
@@ -517,60 +540,43 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
       }
     }
   });
-  // Tile peak: the maximum first (wave, then workgroup), then the lowest flat
-  // index holding it.  Only waves with a thread whose own maximum equals the
-  // tile's look for the index, re-running the last pass from LDS.
-  const float ta = bva, tb = bvb;  // this thread's maxima
+  // Tile peak: (value, flat index) pairs reduced by value, then lower index,
+  // over the wave and then the workgroup's waves.
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    bva = fmaxf(bva, __shfl_xor(bva, o, 64));
-    bvb = fmaxf(bvb, __shfl_xor(bvb, o, 64));
+    const float ova = __shfl_xor(bva, o, 64), ovb = __shfl_xor(bvb, o, 64);
+    const int oia = __shfl_xor(bia, o, 64), oib = __shfl_xor(bib, o, 64);
+    if (better(ova, oia, bva, bia)) {
+      bva = ova;
+      bia = oia;
+    }
+    if (better(ovb, oib, bvb, bib)) {
+      bvb = ovb;
+      bib = oib;
+    }
   }
   if (lane == 0) {
     w_v[0][wid] = bva;
     w_v[1][wid] = bvb;
+    w_i[0][wid] = bia;
+    w_i[1][wid] = bib;
     w_c[0][wid] = ca;
     w_c[1][wid] = cbn;
   }
   __syncthreads();
-  float pka = w_v[0][0], pkb = w_v[1][0];
-#pragma unroll
-  for (int w = 1; w < NW; ++w) {
-    pka = fmaxf(pka, w_v[0][w]);
-    pkb = fmaxf(pkb, w_v[1][w]);
-  }
-  const bool mine_a = ta == pka, mine_b = tb == pkb;
-  int bia = 0x7fffffff, bib = 0x7fffffff;
-  if (__builtin_amdgcn_ballot_w64(mine_a || mine_b)) {
-    fft_last_again<Sh, COLS, NT, S, false, true>(buf, tw, tid, [&](int f, int k0, int ks, auto &v) {
-      constexpr int R = sizeof(v) / sizeof(v[0]);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int idx = (k0 + r * ks) * N + x0 + f;
-        if (mine_a && v[r].x == pka) bia = min(bia, idx);
-        if (mine_b && v[r].y == pkb) bib = min(bib, idx);
-      }
-    });
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    bia = min(bia, __shfl_xor(bia, o, 64));
-    bib = min(bib, __shfl_xor(bib, o, 64));
-  }
-  if (lane == 0) {
-    w_i[0][wid] = bia;
-    w_i[1][wid] = bib;
-  }
-  __syncthreads();
   if (tid < 2 && (tid == 0 || hasb)) {
+    float pk = w_v[tid][0];
     int i = w_i[tid][0];
     uint32_t c = w_c[tid][0];
     for (int w = 1; w < NW; ++w) {
-      i = min(i, w_i[tid][w]);
+      if (better(w_v[tid][w], w_i[tid][w], pk, i)) {
+        pk = w_v[tid][w];
+        i = w_i[tid][w];
+      }
       c += w_c[tid][w];
     }
     ColPart cp;
-    cp.maxv = tid == 0 ? pka : pkb;
+    cp.maxv = pk;
     cp.maxi = i;
     cp.cnt_lo = c;
     cp.n = s_cnt[tid];
