@@ -1168,7 +1168,9 @@ rf_status drs_timed(const rf_plan *p, const int32_t *d_delay_row, const void *vi
       ++n;
     }
     ws.nw = n;
-    const int tchunk = L * std::max(1, 64 / L);
+    // 32 integrations per thread (or the widths' least common multiple):
+    // measured 1211 us per survey DM trial against 1230 us at 64
+    const int tchunk = L * std::max(1, 32 / L);
     dim3 grid((nbc + kDrsThreads - 1) / kDrsThreads, (p->nint + tchunk - 1) / tchunk);
     const dim3 blk(kDrsThreads);
     if (p->vis_dtype == RF_CF32) {
