@@ -396,9 +396,9 @@ __device__ __forceinline__ float buf_load_f1(__amdgpu_buffer_rsrc_t r, uint32_t 
 
 // Launch shapes of the two imaging passes for image side N.
 template <int N>
-struct RowCfg {  // dense rows: F grid rows per workgroup
-  static constexpr int NT = 512;
-  static constexpr int F = (8192 / N) < 64 ? (8192 / N) : 64;
+struct RowCfg {  // dense rows: F grid rows per workgroup (4096 points: ~35 KB LDS)
+  static constexpr int NT = 256;
+  static constexpr int F = (4096 / N) < 64 ? (4096 / N) : 64;
   static constexpr int STRIDE = RowFft<N>::PADDED;
 };
 template <int N>
