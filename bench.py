@@ -34,7 +34,7 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X fp32 vector, published
 # 524,300 KiB for 1 GiB read: x2; WRITE_SIZE 1,049,000 KiB for 1 GiB written:
 # x1).  Valid only for the kernel source with this digest (column kernel
 # section of k_fused.hip, fft.h, rf_internal.h); null once it changes.
-COLS_TRAFFIC = {"digest": "02fa5a8a09df08d4", "fetch_kib": 56808.0, "write_kib": 1428.0,
+COLS_TRAFFIC = {"digest": "f9d3d83d4e280972", "fetch_kib": 56809.0, "write_kib": 1428.0,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 

@@ -404,9 +404,9 @@ struct RowCfg {  // dense rows: F grid rows per workgroup (4096 points: ~35 KB L
 template <int N>
 struct ColCfg {  // columns: COLS columns per workgroup
   // 4 columns from 1024 up (~35 KB LDS at 1024: four workgroups per CU,
-  // whose load and transform phases interleave; ~70 KB at 2048), else 8192
-  // points per workgroup
-  static constexpr int COLS = N >= 1024 ? 4 : (N >= 512 ? 16 : 32 < N ? 32 : N);
+  // whose load and transform phases interleave; ~70 KB at 2048), 8 at 512
+  // (~37 KB), else 8192 points per workgroup
+  static constexpr int COLS = N >= 1024 ? 4 : (N >= 512 ? 8 : 32 < N ? 32 : N);
   static constexpr int FIRST = COLS * N / ColFft<N>::R0;  // first-pass butterflies
   static constexpr int NT = N >= 512 ? (FIRST < 512 ? FIRST : 512) : (FIRST < 256 ? 256 : FIRST);
   // Columns vary fastest across lanes: a 64-bit LDS access serves 16 lanes
