@@ -37,6 +37,13 @@ Functions and the passages they follow:
                 section 3.1 (a second, higher threshold, ~7 sigma, selects
                 candidates for visualisation), 3.3 (the candidate's image
                 and spectrum)
+  dedisperse_window, image_at
+                the same dedispersion and imaging restricted to the
+                integrations of one image (section 2.2, 3.1), for sampling
+                single images of segments too large to search whole
+  is_marginal   the parity margin guard (not a step of the method): images
+                whose S/N or top-two pixel gap lie within 10 tol of a
+                decision may flip between two correct float implementations
 
 Parity pins live in tests/test_oracle_*.py; every function above is pinned
 there against closed forms, brute force, library special cases or the values

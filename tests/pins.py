@@ -317,6 +317,106 @@ def check_noise_sigma(o):
         assert abs(np.mean(sig) / pred - 1) < 0.05, (w, np.mean(sig), pred)
 
 
+# ---------------------------------------------------------------- windowed forms
+
+def _window_case(o):
+    """A small plan whose largest delays reach and pass the segment length,
+    with widths that leave a remainder (T = 13)."""
+    from rfgen import synth
+    uvw = synth.baseline_uvw(synth.y_array_positions(8))
+    f = centres(1.0, 2.0, 10)
+    N = 32
+    du = synth.default_cell_size(uvw, f, N)
+    plan = o.Plan(f, uvw, 0.005, np.array([0.0, 8.0, 30.0]), [1, 2, 4], N, du, du, nint=13)
+    return plan, uvw, f
+
+
+def check_dedisperse_window(o):
+    """Rows [t0, t1) of the dedispersed segment, formed without the rest (for
+    sampling single images of large segments).  A pulse arriving at t* + d[c]
+    in channel c lands at row t* - t0 in every channel whose arrival is inside
+    the segment; rows past T - d[c] hold zeros (delays equal to and beyond T
+    included); the window equals the same rows of the whole-segment
+    dedispersion; float16 storage is widened exactly."""
+    T, B, C, P = 11, 2, 6, 2
+    d = np.array([14, 11, 10, 5, 1, 0], np.int32)
+    ts = 3
+    imp = np.zeros((T, B, C, P), np.complex128)
+    for c in range(C):
+        if ts + d[c] < T:
+            imp[ts + d[c], :, c, :] = 1.0 - 0.5j
+    ones = np.ones((T, B, C, P), np.complex128)
+    rng = np.random.default_rng(33)
+    vis = rng.standard_normal((T, B, C, P)) + 1j * rng.standard_normal((T, B, C, P))
+    whole = o.dedisperse(vis, d)
+    for t0, t1 in [(0, T), (0, 1), (3, 4), (2, 9), (T - 1, T), (4, 7)]:
+        win = o.dedisperse_window(imp, d, t0, t1)
+        assert win.shape == (t1 - t0, B, C, P), win.shape
+        for c in range(C):
+            col = win[:, 0, c, 0]
+            if t0 <= ts < t1 and ts + d[c] < T:
+                assert col[ts - t0] == 1.0 - 0.5j and np.count_nonzero(col) == 1, (t0, t1, c, col)
+            else:
+                assert np.count_nonzero(col) == 0, (t0, t1, c, col)
+        filled = o.dedisperse_window(ones, d, t0, t1)[:, 1, :, 1]
+        for c in range(C):
+            n_in = max(0, min(t1, T - int(d[c])) - t0)
+            assert (filled[:n_in, c] == 1.0).all() and (filled[n_in:, c] == 0.0).all(), (t0, t1, c)
+        assert np.array_equal(o.dedisperse_window(vis, d, t0, t1), whole[t0:t1])
+    v16 = np.zeros((T, B, C, P, 2), np.float16)
+    v16[..., 0] = vis.real.astype(np.float16)
+    v16[..., 1] = vis.imag.astype(np.float16)
+    want = o.dedisperse(v16[..., 0].astype(np.float64) + 1j * v16[..., 1].astype(np.float64), d)
+    assert np.array_equal(o.dedisperse_window(v16, d, 2, 9), want[2:9])
+
+
+def check_image_at(o):
+    """One image of the search, formed from its own window of integrations,
+    is bit for bit the image the whole-segment search forms for that (DM
+    trial, width, integration): every key, trials whose delays reach past the
+    segment and the last box of the widest width included."""
+    plan, uvw, f = _window_case(o)
+    rng = np.random.default_rng(34)
+    vis = rng.standard_normal((13, uvw.shape[0], 10, 2)) + 1j * rng.standard_normal((13, uvw.shape[0], 10, 2))
+    d = plan.delays
+    assert d[2].max() > 13 and 0 < d[1].max() < 13 and (d[2] == 0).any(), d
+    _, _, images = o.search(vis, plan, keep_images=True)
+    assert len(images) == 3 * (13 + 6 + 3)
+    for (i, j, k), img in images.items():
+        got = o.image_at(vis, plan, i, j, k)
+        assert np.array_equal(got, img), (i, j, k, float(np.max(np.abs(got - img))))
+
+
+def check_is_marginal(o):
+    """The margin guard on hand-built images: an S/N within 10 tol (relative)
+    of the threshold, or top two pixels within 10 tol (relative) of each
+    other, is marginal; clear cases are not; an all-zero image is."""
+    def img_with(top, second):
+        a = np.zeros((8, 8))
+        a[:] = np.linspace(-0.5, 0.5, 64).reshape(8, 8)
+        a[2, 5] = top
+        a[6, 1] = second
+        return a
+    tol = 1e-5
+    assert not o.is_marginal(img_with(1.0, 0.9), 7.0, 6.0, tol)
+    # S/N side: |snr - thr| = 3e-4 < 10 tol thr = 6e-4; 9e-4 is not
+    assert o.is_marginal(img_with(1.0, 0.9), 6.0003, 6.0, tol)
+    assert o.is_marginal(img_with(1.0, 0.9), 5.9997, 6.0, tol)
+    assert not o.is_marginal(img_with(1.0, 0.9), 6.0009, 6.0, tol)
+    # gap side: a relative gap of 5e-5 is under 10 tol; 2e-4 is not
+    assert o.is_marginal(img_with(1.0, 1.0 - 5e-5), 7.0, 6.0, tol)
+    assert not o.is_marginal(img_with(1.0, 1.0 - 2e-4), 7.0, 6.0, tol)
+    # relative to the top pixel: the same gap at 100x the scale is the same
+    assert o.is_marginal(img_with(100.0, 100.0 - 5e-3), 7.0, 6.0, tol)
+    assert not o.is_marginal(img_with(100.0, 100.0 - 2e-2), 7.0, 6.0, tol)
+    # a tied top pair is marginal; a lone top pixel far above the rest is not
+    assert o.is_marginal(img_with(1.0, 1.0), 7.0, 6.0, tol)
+    assert o.is_marginal(np.zeros((8, 8)), 0.0, 6.0, tol)
+    # the looser tolerance of float16 storage widens both sides
+    assert o.is_marginal(img_with(1.0, 1.0 - 2e-2), 7.0, 6.0, 3e-3)
+    assert o.is_marginal(img_with(1.0, 0.5), 6.1, 6.0, 3e-3)
+
+
 # ---------------------------------------------------------------- mean subtraction
 
 def check_subtract_mean(o):
@@ -734,5 +834,5 @@ ALL_CHECKS = [
     check_inject_storage_rounding, check_inject_order, check_cutout, check_spectrum_splits_pixel,
     check_spectrum_point_source, check_spectrum_pulse, check_time_spectrum, check_complex_image,
     check_amplitude_stats, check_periodic_pulse_train, check_periodic_dispersed,
-    check_periodic_noise_sigma,
+    check_periodic_noise_sigma, check_dedisperse_window, check_image_at, check_is_marginal,
 ]

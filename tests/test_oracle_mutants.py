@@ -283,6 +283,49 @@ def _periodic_with(zero_freq=False, first_pol=False, no_dd=False):
     return search
 
 
+def _window_with(backwards=False, past_end=False, shift=0):
+    def win(vis, delay_row, t0, t1):
+        T = vis.shape[0]
+        out = np.zeros((t1 - t0,) + tuple(vis.shape[1:4]), complex)
+        for c, d in enumerate(np.asarray(delay_row)):
+            for t in range(t0, t1):
+                s = (t - int(d) if backwards else t + int(d)) + shift
+                if past_end:
+                    ok = s <= T                               # one sample past the end
+                else:
+                    ok = 0 <= s < T
+                if ok:
+                    out[t - t0, :, c, :] = ro.as_complex(vis[s, :, c])
+        return out
+    return win
+
+
+def _image_at_next(vis, plan, i, j, k):               # box starts at k*w + 1
+    w = plan.widths[j]
+    dd = ro.dedisperse_window(vis, plan.delays[i], k * w + 1, k * w + w + 1)
+    return ro.make_image(ro.resample(dd, w)[0], plan)
+
+
+def _image_at_first_width(vis, plan, i, j, k):        # window of width 1
+    dd = ro.dedisperse_window(vis, plan.delays[i], k, k + 1)
+    return ro.make_image(dd[0], plan)
+
+
+def _marginal_with(abs_snr=False, one_tol=False, abs_gap=False, bottom=False):
+    def marg(img, snr, threshold, tol):
+        f = 1 if one_tol else 10
+        lim = f * tol if abs_snr else f * tol * threshold
+        if abs(snr - threshold) < lim:
+            return True
+        flat = np.sort(img.ravel())
+        top, second = (flat[0], flat[1]) if bottom else (flat[-1], flat[-2])
+        if top == 0.0:
+            return True
+        gap = abs(top - second)
+        return (gap if abs_gap else gap / abs(top)) < f * tol
+    return marg
+
+
 MUTANTS = {
     "mean over baselines": dict(subtract_mean=_mean_over_baselines),
     "mean unbiased": dict(subtract_mean=_mean_unbiased),
@@ -329,6 +372,15 @@ MUTANTS = {
     "periodic includes f=0": dict(periodic_search=_periodic_with(zero_freq=True)),
     "periodic first pol": dict(periodic_search=_periodic_with(first_pol=True)),
     "periodic not dedispersed": dict(periodic_search=_periodic_with(no_dd=True)),
+    "window t - d": dict(dedisperse_window=_window_with(backwards=True)),
+    "window reads past the end": dict(dedisperse_window=_window_with(past_end=True)),
+    "window off by one": dict(dedisperse_window=_window_with(shift=1)),
+    "image_at next box": dict(image_at=_image_at_next),
+    "image_at width ignored": dict(image_at=_image_at_first_width),
+    "marginal absolute snr": dict(is_marginal=_marginal_with(abs_snr=True)),
+    "marginal without 10x": dict(is_marginal=_marginal_with(one_tol=True)),
+    "marginal absolute gap": dict(is_marginal=_marginal_with(abs_gap=True)),
+    "marginal bottom pixels": dict(is_marginal=_marginal_with(bottom=True)),
 }
 
 

@@ -76,3 +76,23 @@ def test_cf16_storage_is_widened_exactly():
     z = oracle.as_complex(v16)
     assert z.dtype == np.complex128
     assert np.array_equal(z.real, v16[..., 0].astype(np.float64))
+
+
+@pytest.mark.parametrize("preset", ["tiny", "small"])
+def test_image_at_equals_search_on_every_key(preset):
+    """The windowed image (used to sample single images of segments too large
+    to search whole on the CPU) equals the whole-segment search's image bit
+    for bit on every key of the tiny and small workloads: trials whose delays
+    pass the segment end (tiny: up to 91 integrations against 32) and the
+    last box of the widest width included."""
+    p = rfgen.preset_by_name(preset)
+    plan = plan_of(p)
+    vis = p.make_vis()
+    stats, _, images = oracle.search(vis, plan, keep_images=True)
+    if preset == "tiny":
+        assert plan.delays.max() > p.nint
+    assert len(images) == p.n_images()
+    for (i, j, k), img in images.items():
+        got = oracle.image_at(vis, plan, i, j, k)
+        assert np.array_equal(got, img), (i, j, k)
+        assert oracle.image_stats(got) == stats[(i, j, k)]
