@@ -27,30 +27,33 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 FP32_PEAK_TFLOPS = 157.3    # MI355X fp32 vector, published
 
-# HBM bytes per launch of the column kernel (k_cols_stats, 1024^2 images, 16
-# image pairs per launch), from two rocprofv3 --pmc passes (FETCH_SIZE, then
-# WRITE_SIZE, KiB per dispatch) of `bench.py --dms 2 --profile-only`, each
-# scaled by what the counter reads for a 1 GiB device copy (FETCH_SIZE reads
-# 524,300 KiB for 1 GiB read: x2; WRITE_SIZE 1,049,000 KiB for 1 GiB written:
-# x1).  Valid only for the kernel source with this digest (column kernel
-# section of k_fused.hip, fft.h, rf_internal.h); null once it changes.
-COLS_TRAFFIC = {"digest": "f9d3d83d4e280972", "fetch_kib": 56809.0, "write_kib": 1428.0,
-                "fetch_scale": 2.0, "write_scale": 1.0}
+# HBM bytes per dispatch of the fused search's kernels (survey workload,
+# 1024^2 images, 16 image pairs per batch), from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of `bench.py --dms 2
+# --profile-only`, each scaled by what the counter reads for a 1 GiB device
+# copy (FETCH_SIZE reads 524,300 KiB for 1 GiB read: x2; WRITE_SIZE 1,049,000
+# KiB for 1 GiB written: x1).  Valid only for the kernel sources with this
+# digest (k_fused.hip, fft.h, rf_internal.h); null once they change.
+FUSED_TRAFFIC = {"digest": None, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "kib_per_dispatch": {}}
 
 
-def cols_kernel_digest():
+def fused_kernel_digest():
     import hashlib
     csrc = os.path.join(ROOT, "paper_1802_03084_amd", "csrc")
-    k = open(os.path.join(csrc, "k_fused.hip")).read()
-    a = k.index("// ------------------------------------------------------------------ columns")
-    b = k.index("// ------------------------------------------------------------------ select")
-    h = hashlib.sha256(k[a:b].encode())
-    h.update(open(os.path.join(csrc, "fft.h"), "rb").read())
-    # from the internal header only the device helpers the kernel calls (the
-    # plan struct and host declarations are not part of the kernel's code)
-    r = open(os.path.join(csrc, "rf_internal.h")).read()
-    h.update(r[r.index("// Factor of the paired Hermitian"):r.index("#define RF_HIP_TRY")].encode())
+    h = hashlib.sha256()
+    for f in ("k_fused.hip", "fft.h", "rf_internal.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def traffic_per_dispatch(kind):
+    """Measured HBM bytes of one dispatch of `kind`, or None."""
+    t = FUSED_TRAFFIC
+    if t["digest"] is None or t["digest"] != fused_kernel_digest() or kind not in t["kib_per_dispatch"]:
+        return None
+    fetch, write = t["kib_per_dispatch"][kind]
+    return 1024 * (fetch * t["fetch_scale"] + write * t["write_scale"])
 
 
 def log(*a):
@@ -190,6 +193,16 @@ def _cpu_one(key):
     return key, oracle.image_stats(img)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def event_time(fn, reps, stream):
     import torch
     fn()
@@ -282,7 +295,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--storage", choices=["cf32", "cf16"], default="cf32")
     ap.add_argument("--workload", choices=["survey", "tiny"], default="survey")
-    ap.add_argument("--cpu-images", type=int, default=512)
+    ap.add_argument("--cpu-images", type=int, default=768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain step-chain comparison")
     ap.add_argument("--dms", type=int, default=0,
@@ -299,6 +312,11 @@ def main():
     ap.add_argument("--large", type=int, default=0, metavar="NDM",
                     help="only time the large workload (8192 x 1 ms, 1024 chans, 2048^2) over NDM "
                          "of its 400 DM trials, generated on the device, in both storages")
+    ap.add_argument("--fp16-steps", type=int, default=3,
+                    help="timed steps of the same search with FP16-stored visibilities (0: skip)")
+    ap.add_argument("--large-dms-default", type=int, default=4, metavar="NDM",
+                    help="the large-workload leg of the default run over NDM spread DM trials "
+                         "plus the pulses' trials (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (a plain copy kernel of known size, "
                          "to scale the HBM byte counters) and report its bandwidth")
@@ -353,13 +371,19 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        procs = max(1, min(16, os.cpu_count() or 1))
+        # every core this process may run on, up to the 16 host cores that
+        # go with one GPU on the machines this runs on
+        avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        procs = max(1, min(16, avail))
         n, dt, _ = cpu_baseline(p, vis, args.cpu_images, procs)
-        cpu = {"value": n / dt, "unit": "images/s", "cores": procs, "kind": "oracle",
+        model = cpu_model()
+        cpu = {"value": round(n / dt, 1), "unit": "images/s", "cores": procs, "kind": "oracle",
+               "per_core": round(n / dt / procs, 2), "cpu": model, "cores_available": avail,
                "sample": f"{n} images of the {p.name} workload (4 DM trials spread over the grid x "
                          f"{len(p.widths)} widths x integrations spread over the segment), float64 numpy, "
-                         f"{procs} processes, {dt:.1f} s wall"}
-        log(f"cpu oracle: {n} images in {dt:.1f}s on {procs} processes = {n / dt:.1f} img/s")
+                         f"{procs} processes ({avail} cores available), {dt:.1f} s wall"}
+        log(f"cpu oracle: {n} images in {dt:.1f}s on {procs} processes ({model}) = {n / dt:.1f} img/s, "
+            f"{n / dt / procs:.2f} per core")
 
     import torch
     import paper_1802_03084_amd as rf
@@ -408,6 +432,33 @@ def main():
     log(f"{img_s:.0f} images/s, {step_s * 1e3:.1f} ms/step, RTF {seg_s / step_s:.2f}, "
         f"pulses recovered {found}/{len(p.pulses)}, candidates {n}")
 
+    # The same search with FP16-stored visibilities (float32 arithmetic): the
+    # precision form set against the plain float32 step chain below.
+    fp16 = None
+    if dtype == rf.RF_CF32 and args.fp16_steps > 0:
+        dvis16 = torch.from_numpy(rfgen.to_cf16(vis)).to(dev)
+        plan16 = rf.Plan(p.freq(), p.uvw(), p.tint_s, p.dms, p.widths, p.npix, du, dv, nint=p.nint,
+                         npol=p.npol, vis_dtype=rf.RF_CF16, kdm=p.kdm, threshold=p.threshold)
+        assert plan16.workspace_bytes(rf.RF_OP_SEGMENT) <= ws.numel()
+        plan16.search_segment(dvis16, cap=cap, ws=ws)  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.fp16_steps):
+            rows16, n16, _ = plan16.search_segment(dvis16, cap=cap, ws=ws)
+        torch.cuda.synchronize()
+        t16 = (time.perf_counter() - t) / args.fp16_steps
+        keys16 = {(int(r["dm_idx"]), int(r["width_idx"]), int(r["t_int"]), int(r["x"]), int(r["y"]))
+                  for r in rows16}
+        fp16 = {"path": "rf_search_segment (fused), cf16 storage, f32 arithmetic",
+                "steps": args.fp16_steps, "ms_per_step": round(t16 * 1e3, 1),
+                "images_per_s": round(plan16.n_images / t16, 1), "rtf": round(seg_s / t16, 3),
+                "candidates": n16, "candidates_shared_with_cf32": len(keys16 & keys),
+                "pulses_recovered": f"{sum((q.dm_idx, q.width_idx, q.t0, q.x, q.y) in keys16 for q in p.pulses)}"
+                                    f"/{len(p.pulses)}"}
+        log(f"fp16 storage: {plan16.n_images / t16:.0f} images/s, {t16 * 1e3:.1f} ms/step, "
+            f"{n16} candidates ({len(keys16 & keys)} shared with cf32)")
+        del dvis16, plan16
+
     N = p.npix
     nw = len(p.widths)
     n_rows = plan.info["n_rows"]
@@ -438,32 +489,42 @@ def main():
     launches = per_step[dom]
     avg_s = kernels[dom]["avg_us"] * 1e-6
     b_launch, f_launch = bytes_step / launches, flops_step / launches
-    # The roofline that binds is the longer of the two lower bounds on the
-    # kernel's time (its algorithmic bytes at the HBM peak, its algorithmic
-    # flops at the fp32 vector peak): below the ridge point (peak flops / peak
-    # bandwidth) a kernel is HBM-bound.
-    hbm_bound = b_launch / (HBM_PEAK_GBS * 1e9) >= f_launch / (FP32_PEAK_TFLOPS * 1e12)
     gbs = b_launch / avg_s / 1e9
     tfs = f_launch / avg_s / 1e12
-    if hbm_bound:
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
-    else:
+    # The transforms' algorithmic work is their flops (5 N log2 N per length-N
+    # complex transform; nothing is counted for the row-transformed batch they
+    # hand each other through memory, an intermediate of this design), done by
+    # the fp32 vector units: their roofline is the fp32 vector peak.  The
+    # passes over the segment (dedispersion, gridding) do no flops: theirs is
+    # the HBM peak.
+    if f_launch:
         roof = {"bound": "alu", "kernel": dom, "achieved": round(tfs, 2), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(tfs / FP32_PEAK_TFLOPS, 4), "traffic": None}
-    roof.update({"avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": b_launch,
-                 "alg_flops_per_launch": f_launch, "launches_per_step": launches,
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    roof.update({"avg_launch_us": round(avg_s * 1e6, 2), "alg_flops_per_launch": f_launch,
+                 "alg_bytes_per_launch": b_launch, "launches_per_step": launches,
                  "timing": "HIP start/stop events attached to each dispatch (hipExtLaunchKernel) "
                            "on the launch's stream, one search with the launches in order on one "
                            "stream (the kernel alone on the device)"})
     if f_launch:
-        roof["intensity_flop_per_B"] = round(f_launch / b_launch, 2)
-        roof["ridge_flop_per_B"] = round(FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9), 2)
-        roof["fp32"] = {"achieved_tflops": round(tfs, 2), "frac": round(tfs / FP32_PEAK_TFLOPS, 4)}
-    if dom == "cols" and N == 1024 and cols_kernel_digest() == COLS_TRAFFIC["digest"]:
-        t = COLS_TRAFFIC
-        roof["traffic"] = round(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
-        roof["traffic_unit"] = "B per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)"
+        # the packed fp32 forms are not used (they are switched off in the
+        # build): one fp32 FMA per lane per cycle is half the published peak
+        roof["unpacked_fp32_peak_tflops"] = round(FP32_PEAK_TFLOPS / 2, 2)
+        roof["frac_of_unpacked"] = round(tfs / (FP32_PEAK_TFLOPS / 2), 4)
+    if N == 1024 and traffic_per_dispatch(dom) is not None:
+        roof["traffic"] = round(traffic_per_dispatch(dom))
+        roof["traffic_unit"] = ("B per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE): for the "
+                                "transforms, the row-transformed batch passed through memory, an "
+                                "intermediate the algorithmic figure does not count")
+    # the whole step's algorithmic HBM bytes (the segment read once per DM
+    # trial) against the HBM bytes its kernels move (counters)
+    roof["step_alg_bytes"] = len(p.dms) * in_bytes
+    if N == 1024 and all(traffic_per_dispatch(k) is not None for k in per_step):
+        moved = sum(traffic_per_dispatch(k) * per_step[k] for k in per_step)
+        roof["step_traffic_bytes"] = round(moved)
+        roof["step_traffic_over_alg"] = round(moved / roof["step_alg_bytes"], 2)
     for k in algo:
         if k in kernels and k in per_step:
             by, fl = algo[k]
@@ -502,6 +563,8 @@ def main():
                  "same_candidates": keys_p == keys}
         log(f"plain step chain: {tp:.2f}s/step, {plan.n_images / tp:.0f} images/s, same candidates {keys_p == keys}")
         del wsp
+        if fp16:
+            fp16["speedup_vs_plain_fp32"] = round(tp / (fp16["ms_per_step"] * 1e-3), 2)
 
     periodic = None
     if not args.no_periodic and (p.nint & (p.nint - 1)) == 0:
@@ -530,6 +593,11 @@ def main():
         del ws, dvis
         torch.cuda.empty_cache()
         serving = serving_leg(args.serving_speedup, args.serving_segments, args.serving_slots, "cf16")
+
+    large = None
+    if args.large_dms_default > 0 and not args.dms:
+        torch.cuda.empty_cache()
+        large = large_leg(args.large_dms_default, 1)
 
     out = {
         "metric": "images searched/sec",
@@ -560,6 +628,8 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "periodic": periodic,
+        "fp16_storage": fp16,
+        "large": large,
     }
     print(json.dumps(out), flush=True)
 

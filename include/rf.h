@@ -320,11 +320,19 @@ rf_status rf_server_create(void *d_arena, size_t arena_bytes, int32_t nslots, rf
 /* Releases one segment: h_vis is host memory in the plan's segment layout
  * (pinned memory makes the copy asynchronous); it and the plan must stay
  * valid until rf_server_wait returns for the ticket.  Returns at once.
- * flags: 0, or RF_SERVE_SUBTRACT_MEAN to run rf_subtract_mean on the device
- * copy before the search.  RF_EWORKSPACE if the request could never fit in
- * the arena, RF_EINVAL on NULL arguments, unknown flags or after
- * rf_server_destroy began, RF_ERANGE if cap < 0. */
-enum { RF_SERVE_SUBTRACT_MEAN = 1 };
+ * flags: 0 or a combination of
+ *   RF_SERVE_SUBTRACT_MEAN    run rf_subtract_mean on the device copy before
+ *                             the search;
+ *   RF_SERVE_FAIL_AFTER_COPY  fault injection for tests of the error path:
+ *                             the slot enqueues the copy (and the mean
+ *                             subtraction) and then fails the request with
+ *                             RF_EHIP without searching.
+ * A request that fails has its slot stream drained before its arena block is
+ * reused, so no later request is admitted into memory still being written.
+ * RF_EWORKSPACE if the request could never fit in the arena, RF_EINVAL on
+ * NULL arguments, unknown flags or after rf_server_destroy began, RF_ERANGE
+ * if cap < 0. */
+enum { RF_SERVE_SUBTRACT_MEAN = 1, RF_SERVE_FAIL_AFTER_COPY = 2 };
 rf_status rf_server_submit(rf_server *server, const rf_plan *plan, const void *h_vis, int32_t cap,
                            int32_t flags, int64_t *ticket);
 
@@ -440,6 +448,16 @@ rf_status rf_search_periodic(const rf_plan *plan, const void *d_vis, rf_candidat
  * higher threshold, typically 7 sigma, get visualisations; section 3.3: the
  * candidate's image and spectrum).
  * ------------------------------------------------------------------------ */
+
+/* The second tier itself: copies, in order, the rows of h_in[0..n) whose
+ * snr exceeds `threshold` (strictly; section 3.1 names about 7 sigma) to
+ * h_out, at most cap of them; *nout receives the number of rows that pass
+ * (which may exceed cap).  Host memory only; nothing runs on the device.
+ * h_out may equal h_in (filtering in place).  RF_EINVAL on NULL (h_in and
+ * h_out may be NULL when n, respectively cap, is 0), RF_ERANGE if n < 0,
+ * cap < 0 or the threshold is not finite. */
+rf_status rf_select_tier(const rf_candidate *h_in, int32_t n, float threshold,
+                         rf_candidate *h_out, int32_t cap, int32_t *nout);
 
 /* Workspace of rf_candidate_products for nspec spectrum rows: the gathered
  * rows (nspec x nbl x nchan x npol complex64), one grid, one image and the

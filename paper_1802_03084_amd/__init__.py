@@ -36,9 +36,14 @@ TAG_DTYPE = np.dtype([("dm_idx", "<i4"), ("width_idx", "<i4"), ("t_int", "<i4")]
 
 def second_tier(rows, threshold=7.0):
     """Candidates above the second, higher threshold (section 3.1: about 7
-    sigma), which get image cutouts and spectra."""
-    rows = np.asarray(rows)
-    return rows[rows["snr"] > threshold]
+    sigma), which get image cutouts and spectra (rf_select_tier)."""
+    rows = np.ascontiguousarray(rows, dtype=CAND_DTYPE)
+    out = np.empty(len(rows), dtype=CAND_DTYPE)
+    k = ctypes.c_int32()
+    _lib.check(_lib.load().rf_select_tier(rows.ctypes.data_as(ctypes.c_void_p), len(rows),
+                                          float(threshold), out.ctypes.data_as(ctypes.c_void_p),
+                                          len(out), ctypes.byref(k)), "rf_select_tier")
+    return out[: k.value]
 
 
 def load_library():
@@ -413,9 +418,13 @@ class Server:
                    "rf_server_request_bytes")
         return n.value
 
-    def submit(self, plan, h_vis, cap=4096, subtract_mean=False):
+    SUBTRACT_MEAN = 1
+    FAIL_AFTER_COPY = 2  # fault injection: the request fails after its copy is enqueued
+
+    def submit(self, plan, h_vis, cap=4096, subtract_mean=False, flags=0):
         """Releases one segment; returns its ticket at once.  subtract_mean:
-        the segment's time mean is subtracted on the device before the search."""
+        the segment's time mean is subtracted on the device before the search.
+        flags: further rf_server_submit flags (FAIL_AFTER_COPY for tests)."""
         torch = _torch()
         want_dt = torch.complex64 if plan.vis_dtype == RF_CF32 else torch.float16
         want = (plan.nint, plan.nbl, plan.nchan, plan.npol) + (() if want_dt == torch.complex64 else (2,))
@@ -425,7 +434,8 @@ class Server:
                              f"{tuple(h_vis.shape)} on {h_vis.device}")
         t = ctypes.c_int64()
         _lib.check(_lib.load().rf_server_submit(self._h, plan.handle, _ptr(h_vis), int(cap),
-                                                1 if subtract_mean else 0, ctypes.byref(t)),
+                                                int(flags) | (self.SUBTRACT_MEAN if subtract_mean else 0),
+                                                ctypes.byref(t)),
                    "rf_server_submit")
         self._keep[t.value] = (plan, h_vis, int(cap))
         return t.value

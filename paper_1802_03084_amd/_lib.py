@@ -122,6 +122,7 @@ SIGNATURES = {
     "rf_products_workspace_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_size)]),
     "rf_candidate_products": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp,
                                       c_size, c_vp]),
+    "rf_select_tier": (c_i32, [c_vp, c_i32, ctypes.c_float, c_vp, c_i32, ctypes.POINTER(c_i32)]),
     "rf_batch_workspace_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_size)]),
     "rf_batch_create": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp,
                                 ctypes.POINTER(c_vp)]),

@@ -1070,6 +1070,12 @@ struct Lanes {
     return e;
   }
   ~Lanes() {
+    // a search that returned early (an error part way) can leave work on the
+    // lane streams that the caller's stream never joined: let it finish
+    // before the caller reuses the buffers (instant on the normal path)
+    for (int k = 0; k < kMaxLanes; ++k)
+      if (lane[k]) (void)hipStreamSynchronize(lane[k]);
+    if (drs) (void)hipStreamSynchronize(drs);
     auto de = [](hipEvent_t x) {
       if (x) (void)hipEventDestroy(x);
     };
@@ -1221,8 +1227,12 @@ rf_status segment_enqueue(const rf_plan *p, const void *vis, rf_candidate *cand,
   if (st != RF_OK) return st;
   if (p->W == 0 || p->n_rows == 0) {
     // nothing is gridded: every image is identically zero; the step chain
-    // produces the (zero) statistics
-    return run_segment_steps(p, vis, cand, cap, ncand, stats, ws, ws_bytes, s);
+    // produces the (zero) statistics.  Its buffers start at the workspace's
+    // first byte and can cover the fallback list, so the count is cleared
+    // again after it (stream order): no image needs the exact recomputation.
+    st = run_segment_steps(p, vis, cand, cap, ncand, stats, ws, ws_bytes, s);
+    if (st != RF_OK) return st;
+    return launch_zero_i32(fb, 1, s);
   }
   // The lane streams take the batches round robin and a stream of its own
   // runs each DM's pass over the segment into the sample buffer of that DM's

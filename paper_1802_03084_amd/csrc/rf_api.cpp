@@ -475,6 +475,21 @@ rf_status rf_candidate_products(const rf_plan *p, const void *d_vis, const rf_ca
                       (hipStream_t)stream);
 }
 
+rf_status rf_select_tier(const rf_candidate *h_in, int32_t n, float threshold,
+                         rf_candidate *h_out, int32_t cap, int32_t *nout) {
+  if (!nout || (n > 0 && !h_in) || (cap > 0 && !h_out)) return RF_EINVAL;
+  if (n < 0 || cap < 0 || !std::isfinite(threshold)) return RF_ERANGE;
+  int32_t k = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (h_in[i].snr > threshold) {
+      if (k < cap) h_out[k] = h_in[i];  // k <= i: in place is safe
+      ++k;
+    }
+  }
+  *nout = k;
+  return RF_OK;
+}
+
 rf_status rf_plan_set_tuning(rf_plan *p, int32_t lanes, int32_t m_budget_mb) {
   if (!p) return RF_EINVAL;
   if (lanes < 1 || lanes > 4 || m_budget_mb < 16 || m_budget_mb > 4096) return RF_ERANGE;

@@ -129,6 +129,7 @@ rf_status serve_one(rf_server *sv, Request *r, hipStream_t s) {
     const rf_status sm = launch_mean_subtract(r->plan, d_vis, s);
     if (sm != RF_OK) return sm;
   }
+  if (r->flags & RF_SERVE_FAIL_AFTER_COPY) return RF_EHIP;  // fault injection (tests)
   const rf_status st = rf_search_segment(r->plan, d_vis, d_cand, r->cap, d_ncand, nullptr, d_ws,
                                          r->ws_bytes, s);
   if (st != RF_OK) return st;
@@ -172,6 +173,11 @@ void worker(rf_server *sv) {
       r->started = Clock::now();
     }
     const rf_status st = ok ? serve_one(sv, r, s) : RF_EHIP;
+    // A request that failed part way may still have a copy or kernels in
+    // flight on s (the search joins its own lane streams before it returns):
+    // drain s before its block goes back to the arena, so that no later
+    // request is admitted into memory that is still being written.
+    if (st != RF_OK && s) (void)hipStreamSynchronize(s);
     {
       std::lock_guard<std::mutex> lk(sv->m);
       sv->arena.release(r->off, r->bytes);
@@ -220,7 +226,7 @@ rf_status rf_server_submit(rf_server *sv, const rf_plan *p, const void *h_vis, i
                            int32_t flags, int64_t *ticket) {
   if (!sv || !p || !h_vis || !ticket) return RF_EINVAL;
   if (cap < 0) return RF_ERANGE;
-  if (flags & ~RF_SERVE_SUBTRACT_MEAN) return RF_EINVAL;
+  if (flags & ~(RF_SERVE_SUBTRACT_MEAN | RF_SERVE_FAIL_AFTER_COPY)) return RF_EINVAL;
   Request *r = new Request();
   r->plan = p;
   r->h_vis = h_vis;

@@ -171,3 +171,28 @@ def test_periodic_arguments_rejected_without_gpu():
     n = ctypes.c_size_t(0)
     assert L.rf_periodic_workspace_bytes(None, ctypes.byref(n)) == -1
     assert L.rf_search_periodic(None, None, None, 0, None, None, None, 0, None) == -1
+
+
+def test_select_tier_keeps_rows_above_the_second_threshold():
+    """rf_select_tier (host only): rows with snr strictly above the tier's
+    threshold, in order; the count is the true count when cap is short; in
+    place works; bad arguments are rejected."""
+    L = lib()
+    import paper_1802_03084_amd as rf
+    rows = np.zeros(6, dtype=rf.CAND_DTYPE)
+    rows["snr"] = [5.0, 7.5, 7.0, 9.0, 6.9, 12.0]
+    rows["dm_idx"] = np.arange(6)
+    got = rf.second_tier(rows, 7.0)
+    assert list(got["dm_idx"]) == [1, 3, 5]
+    out = np.zeros(2, dtype=rf.CAND_DTYPE)
+    k = ctypes.c_int32()
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    assert L.rf_select_tier(vp(rows), 6, ctypes.c_float(7.0), vp(out), 2, ctypes.byref(k)) == 0
+    assert k.value == 3 and list(out["dm_idx"]) == [1, 3]
+    inplace = rows.copy()
+    assert L.rf_select_tier(vp(inplace), 6, ctypes.c_float(6.0), vp(inplace), 6, ctypes.byref(k)) == 0
+    assert k.value == 5 and list(inplace["dm_idx"][:5]) == [1, 2, 3, 4, 5]
+    assert L.rf_select_tier(None, 0, ctypes.c_float(7.0), None, 0, ctypes.byref(k)) == 0 and k.value == 0
+    assert L.rf_select_tier(vp(rows), -1, ctypes.c_float(7.0), vp(out), 2, ctypes.byref(k)) == -3
+    assert L.rf_select_tier(vp(rows), 6, ctypes.c_float(float("nan")), vp(out), 2, ctypes.byref(k)) == -3
+    assert L.rf_select_tier(vp(rows), 6, ctypes.c_float(7.0), None, 2, ctypes.byref(k)) == -1

@@ -47,6 +47,27 @@ def test_nothing_gridded(torch):
     assert float(cut.abs().max()) == 0.0 and float(spec.abs().max()) == 0.0
 
 
+def test_nothing_gridded_survey_shape(torch):
+    """W = 0 at the survey shape (351 baselines x 256 channels, 2048
+    integrations, 1024^2) with DM trials over 0-500: the step chain that
+    produces the zero statistics fills buffers that cover the fused path's
+    fallback list, and with the top DM under the full sweep those buffers hold
+    data.  No image may be sent to the exact recomputation, twice in a row."""
+    p = rfgen.survey()
+    p.dms = np.linspace(0, 500, 8)
+    p.pulses = []
+    du, dv = p.cell()
+    g = gpu_plan(p, du=du * 1e-3, dv=dv * 1e-3)
+    assert g.W == 0
+    vis = upload(p.make_vis())
+    for rep in range(2):
+        say("nothing gridded, survey shape, run", rep)
+        times, rows, n = g.profile_segment(vis, cap=64)
+        assert n == 0 and times["fallback"][1] == 0, times
+        rows, n, st = g.search_segment(vis, cap=64, with_stats=True)
+        assert n == 0 and (st["peak"] == 0).all() and (st["snr"] == 0).all()
+
+
 def test_widths_up_to_the_segment(torch):
     """A width equal to the segment length gives one image per DM trial (as
     the oracle's); a width longer than the segment is rejected."""

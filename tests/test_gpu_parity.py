@@ -269,3 +269,65 @@ def test_profile_modes_match_search(torch):
                                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), None,
                                                ctypes.byref(kt))
     assert st == _lib.RF_EINVAL
+
+
+def _band_preset(n, nint, pulses=(), seed=13):
+    """Few integrations of the survey band (1024^2: 256 channels over 1-2 GHz,
+    10 ms) or of the large band (2048^2: 1024 channels over 2-4 GHz, 1 ms)."""
+    if n == 1024:
+        return rfgen.Preset(name="survey-band", nant=27, nint=nint, tint_s=0.010, f_lo_ghz=1.0,
+                            f_hi_ghz=2.0, nchan=256, npol=2, dms=np.array([0.0, 40.0]),
+                            widths=[1, 2], npix=n, seed=seed, pulses=list(pulses))
+    return rfgen.Preset(name="large-band", nant=27, nint=nint, tint_s=0.001, f_lo_ghz=2.0,
+                        f_hi_ghz=4.0, nchan=1024, npol=2, dms=np.array([0.0, 30.0]),
+                        widths=[1, 2], npix=n, seed=seed, pulses=list(pulses))
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_image_full_size_elementwise(torch, n):
+    """rf_image, the dense transform of the exact fallback, the second-tier
+    products and the periodicity search, element by element against the
+    oracle's image at the survey (1024^2) and large (2048^2) sizes: three
+    images, the last without a partner in its transform pair."""
+    p = _band_preset(n, 3)
+    say("rf_image element-wise", n)
+    vis = p.make_vis()
+    g = gpu_plan(p)
+    o = oracle_plan(p)
+    img = g.image(g.grid(upload(vis))).cpu().numpy()
+    for k in range(p.nint):
+        G = oracle.grid(oracle.stokes_i(vis[k].astype(np.complex128)), o.iu, o.iv, o.valid, n)
+        ref = oracle.image(G, o.W)
+        e = rel_err(img[k], ref)
+        say(f"  image {k}: max |diff| / max |ref| = {e:.2e}")
+        assert e < TOL32, (k, e)
+
+
+def test_fused_bright_source_exact_fallback_2048(torch):
+    """The exact fallback at 2048^2: a very bright pulse moves the rms far
+    from the noise median, the bracket misses, the image is recomputed by the
+    dense step chain; fused and step results are identical and sigma matches
+    the oracle's exact lower median."""
+    n = 2048
+    p = _band_preset(n, 6, [rfgen.Pulse(dm_idx=1, width_idx=0, t0=2, x=n // 2 + 70, y=n // 2 - 41,
+                                        snr=600.0)])
+    say("bright source fallback 2048")
+    g = gpu_plan(p)
+    o = oracle_plan(p)
+    vis = p.make_vis()
+    dv = upload(vis)
+    times, _, _ = g.profile_segment(dv, cap=4096)
+    assert times["fallback"][1] >= 1, times
+    r1, n1, s1 = g.search_segment(dv, cap=4096, with_stats=True)
+    r2, n2, s2 = g.search_segment(dv, cap=4096, with_stats=True, steps=True)
+    assert np.array_equal(s1.view(np.int32), s2.view(np.int32))
+    assert np.array_equal(r1, r2)
+    key = (1, 0, 2)
+    st, _, im = oracle.search(vis, o, select={key}, keep_images=True)
+    peak, x, y, sigma, snr = st[key]
+    s = s1[g.image_base(1, 0) + 2]
+    assert (int(s["x"]), int(s["y"])) == (x, y) == (n // 2 + 70, n // 2 - 41)
+    amax = float(np.max(np.abs(im[key])))
+    assert abs(s["peak"] - peak) <= TOL32 * amax
+    assert abs(s["sigma"] - sigma) <= 1.4826 * TOL32 * amax
+    assert s["snr"] > 50

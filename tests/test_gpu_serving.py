@@ -7,8 +7,9 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
 import rfgen
-from helpers import cand_keys, gpu_plan, upload
+from helpers import cand_keys, gpu_plan, oracle_plan, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -107,3 +108,51 @@ def test_request_larger_than_arena_rejected(torch, segments):
         srv.submit(g, h, cap=4096)
     assert e.value.status == -4
     srv.close()
+
+
+def test_failed_request_is_drained_before_its_memory_is_reused(torch, segments):
+    """A request that fails after its copy was enqueued (fault injection) must
+    not leave work in flight in its arena block: with an arena that holds one
+    request and two slots, the next request is admitted into the same block
+    on the other slot, and its results must equal the alone run."""
+    import paper_1802_03084_amd as rf
+    p, g, h, rows0, n0 = segments[2]
+    need = rf.Server.request_bytes(g, 4096)
+    arena = torch.empty(need + need // 2, dtype=torch.uint8, device="cuda")
+    srv = rf.Server(arena, nslots=2)
+    say("serving: failed request, then reuse of its block")
+    for rep in range(3):
+        bad = srv.submit(g, h, cap=4096, flags=rf.Server.FAIL_AFTER_COPY)
+        good = srv.submit(g, h, cap=4096)
+        with pytest.raises(rf.RFError) as e:
+            srv.wait(bad)
+        assert e.value.status == -5
+        rows, n, _ = srv.wait(good)
+        assert n == n0 and np.array_equal(rows, rows0), rep
+    srv.close()
+
+
+def test_served_results_match_the_oracle(torch, segments):
+    """The served segments' candidate keys against the CPU oracle (float32
+    storage: 1e-5 bar; FP16 storage: 3e-3 against the oracle on the unrounded
+    input), images inside the margin guard excluded and counted."""
+    import paper_1802_03084_amd as rf
+    need = sum(rf.Server.request_bytes(g, 4096) for _, g, _, _, _ in segments)
+    arena = torch.empty(need + (1 << 20), dtype=torch.uint8, device="cuda")
+    srv = rf.Server(arena, nslots=3)
+    tickets = [srv.submit(g, h, cap=4096) for _, g, h, _, _ in segments]
+    served = [srv.wait(t) for t in tickets]
+    srv.close()
+    for (p, g, h, _, _), (rows, n, _) in zip(segments, served):
+        tol = 1e-5 if g.vis_dtype == 0 else 3e-3
+        vis = p.make_vis()
+        o = oracle_plan(p)
+        ostats, ocands, oimgs = oracle.search(vis, o, keep_images=True)
+        marginal = {key for key, st in ostats.items()
+                    if oracle.is_marginal(oimgs[key], st[4], o.threshold, tol)}
+        want = [c[:5] for c in ocands if (c[0], c[1], c[2] // p.widths[c[1]]) not in marginal]
+        got = [k for k in cand_keys(rows) if (k[0], k[1], k[2] // p.widths[k[1]]) not in marginal]
+        say("served vs oracle", p.name, "storage", g.vis_dtype, "candidates", n, "marginal", len(marginal))
+        assert got == want
+        q = p.pulses[0]
+        assert (q.dm_idx, q.width_idx, q.t0, q.x, q.y) in cand_keys(rows)
