@@ -288,6 +288,73 @@ def large_leg(ndm, steps):
     return out
 
 
+def batching_leg(dms_per_segment):
+    """The batching workload: 64 segments of uneven shape (nint 256-4096,
+    128-512 channels, 512^2 to 2048^2 images, 64-254 DM trials each),
+    FP16-stored visibilities generated on the device, all resident in HBM and
+    searched as one batch (rf_batch_run).  Each segment keeps
+    `dms_per_segment` of its DM trials spread over its grid plus the pulse's
+    trial (every DM trial of a segment costs the same), so the run takes
+    seconds; images/s is measured over the batch and the full workload's time
+    projected from the per-segment DM fractions."""
+    import numpy as np
+    import torch
+    import rfgen
+    import paper_1802_03084_amd as rf
+    from paper_1802_03084_amd import mock
+    plans, segs, meta = [], [], []
+    t = time.perf_counter()
+    for s in range(rfgen.BATCHING_SEGMENTS):
+        ndm = rfgen.batching_dm_count(s)
+        keep = sorted(set(np.linspace(0, ndm - 1, dms_per_segment).round().astype(int).tolist())
+                      | {ndm // 3})
+        p = rfgen.batching(s, keep_dms=keep)
+        du, dv = p.cell()
+        plan = rf.Plan(p.freq(), p.uvw(), p.tint_s, p.dms, p.widths, p.npix, du, dv, nint=p.nint,
+                       npol=p.npol, vis_dtype=rf.RF_CF16, kdm=p.kdm, threshold=p.threshold)
+        segs.append(mock.synthesize(plan, p.seed, p.mocks()))
+        plans.append(plan)
+        meta.append((p, ndm, len(keep)))
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    seg_bytes = sum(v.numel() * v.element_size() for v in segs)
+    b = rf.Batch(plans, segs, cap=65536)
+    log(f"batching: {len(plans)} segments, {seg_bytes / 1e9:.1f} GB FP16 resident, workspace "
+        f"{b.ws.numel() / 1e9:.1f} GB, generated in {gen_s:.1f} s")
+    b.run()  # warm (first use of every shape)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = b.run()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    imgs = sum(pl.n_images for pl in plans)
+    found = total = 0
+    full_s = 0.0
+    per_n = {}
+    for (p, ndm, kept), pl, (rows, n, _) in zip(meta, plans, res):
+        keys = {(int(r["dm_idx"]), int(r["width_idx"]), int(r["t_int"]), int(r["x"]), int(r["y"])) for r in rows}
+        for q in p.pulses:
+            total += 1
+            found += (q.dm_idx, q.width_idx, q.t0, q.x, q.y) in keys
+        per_n[p.npix] = per_n.get(p.npix, 0) + pl.n_images
+    # projected full workload: each segment's share of the wall time scales
+    # with its full DM count over the kept ones
+    full_imgs = sum(p.n_images() // kept * ndm for (p, ndm, kept) in meta)
+    out = {"workload": "batching: 64 segments, nint 256-4096, 128-512 chans, 351 baselines, 5 ms, "
+                       "1-2 GHz, widths [1,2,4,8], 512^2-2048^2 images, FP16 storage, generated on "
+                       f"the device; {dms_per_segment} spread DM trials per segment + the pulse's",
+           "segments": len(plans), "images_per_run": imgs, "images_by_npix": per_n,
+           "ms_per_run": round(wall * 1e3, 1), "images_per_s": round(imgs / wall, 1),
+           "resident_GB": round(seg_bytes / 1e9, 2), "pulses_recovered": f"{found}/{total}",
+           "full_workload_images": full_imgs,
+           "full_workload_projected_s": round(full_imgs / (imgs / wall), 1),
+           "path": "rf_batch_run (eager: graph capture is switched off)"}
+    log(f"batching: {imgs / wall:.0f} images/s over {imgs} images in {wall:.2f} s, pulses {found}/{total}")
+    del b, segs, plans
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +384,9 @@ def main():
     ap.add_argument("--large-dms-default", type=int, default=4, metavar="NDM",
                     help="the large-workload leg of the default run over NDM spread DM trials "
                          "plus the pulses' trials (0: skip)")
+    ap.add_argument("--batching-dms", type=int, default=3, metavar="NDM",
+                    help="the batching leg: NDM spread DM trials per segment plus the pulse's (0: skip)")
+    ap.add_argument("--batching-only", action="store_true", help="run only the batching leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (a plain copy kernel of known size, "
                          "to scale the HBM byte counters) and report its bandwidth")
@@ -354,6 +424,10 @@ def main():
 
     if args.large:
         print(json.dumps({"large": large_leg(args.large, args.steps)}), flush=True)
+        return
+
+    if args.batching_only:
+        print(json.dumps({"batching": batching_leg(args.batching_dms or 3)}), flush=True)
         return
 
     if args.serving_only:
@@ -594,6 +668,11 @@ def main():
         torch.cuda.empty_cache()
         serving = serving_leg(args.serving_speedup, args.serving_segments, args.serving_slots, "cf16")
 
+    batching = None
+    if args.batching_dms > 0 and not args.dms:
+        torch.cuda.empty_cache()
+        batching = batching_leg(args.batching_dms)
+
     large = None
     if args.large_dms_default > 0 and not args.dms:
         torch.cuda.empty_cache()
@@ -629,6 +708,7 @@ def main():
         "serving": serving,
         "periodic": periodic,
         "fp16_storage": fp16,
+        "batching": batching,
         "large": large,
     }
     print(json.dumps(out), flush=True)

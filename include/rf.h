@@ -501,35 +501,43 @@ rf_status rf_candidate_products(const rf_plan *plan, const void *d_vis, const rf
 rf_status rf_plan_set_tuning(rf_plan *plan, int32_t lanes, int32_t m_budget_mb);
 
 /* A batch: the fused searches of nseg segments (plans of any shapes) bound
- * once and run by one rf_batch_run call.  The segments run in order and
- * share one workspace.  (Graph capture of the batch is switched off: see
- * rf_batch_run.) */
+ * once and run by one rf_batch_run call (section 3.2: segments are
+ * independent units of work).  The segments run in order and share one
+ * workspace. */
 typedef struct rf_batch rf_batch;
 
 /* Workspace of a batch over plans[0..nseg): the largest segment workspace
  * plus one fallback list per segment. */
 rf_status rf_batch_workspace_bytes(const rf_plan *const *plans, int32_t nseg, size_t *bytes);
 
-/* Binds the batch (stream: reserved, may be NULL).
- * Every buffer is bound now and read or written by every rf_batch_run: per
- * segment i, d_vis[i] (the plan's segment layout), d_cand[i] (cap[i] rows),
- * d_ncand[i], d_stats[i] (d_stats may be NULL, or entries NULL); d_ws of
- * rf_batch_workspace_bytes.  All caller-owned and kept alive until
- * rf_batch_destroy.  Nothing runs until rf_batch_run.  RF_EINVAL on NULL
- * arguments or nseg < 1, RF_ERANGE on a negative cap, RF_EWORKSPACE if ws is
- * too small, RF_EHIP if the batch's streams cannot be created. */
+/* rf_batch_create flags. */
+enum { RF_BATCH_GRAPH = 1 };
+
+/* Binds the batch.  Every buffer is bound now and read or written by every
+ * rf_batch_run: per segment i, d_vis[i] (the plan's segment layout),
+ * d_cand[i] (cap[i] rows), d_ncand[i], d_stats[i] (d_stats may be NULL, or
+ * entries NULL); d_ws of rf_batch_workspace_bytes.  All caller-owned and
+ * kept alive until rf_batch_destroy; the plans must not be retuned meanwhile.
+ * flags: 0.  RF_BATCH_GRAPH (capture every segment's search once into HIP
+ * graphs, each run a few graph launches) is refused with RF_EUNSUPPORTED in
+ * this build: its runs ended the host process with a segmentation fault
+ * inside the capture, with no cause found in the capture sequence.  Nothing
+ * runs on the device until rf_batch_run.  RF_EINVAL on NULL arguments,
+ * nseg < 1 or unknown flags, RF_ERANGE on a negative cap, RF_EWORKSPACE if
+ * ws is too small, RF_EHIP if the batch's streams cannot be created (nothing
+ * is left allocated). */
 rf_status rf_batch_create(const rf_plan *const *plans, int32_t nseg, const void *const *d_vis,
                           rf_candidate *const *d_cand, const int32_t *cap,
                           int32_t *const *d_ncand, rf_image_stats *const *d_stats, void *d_ws,
-                          size_t ws_bytes, void *stream, rf_batch **out);
+                          size_t ws_bytes, int32_t flags, rf_batch **out);
 
-/* Enqueues every segment's fused search on `stream` (with the batch's lane
- * streams: the end of one segment overlaps the start of the next), then
- * recomputes exactly the images whose median left the bracket (one
- * synchronisation of `stream` per segment).  Results as rf_search_segment on
- * each segment.  Capturing the batch into one HIP graph is switched off: its
- * one run crashed the host process inside the stream capture, with no cause
- * found in this library's capture sequence. */
+/* Nodes of the batch's captured graph (0 without RF_BATCH_GRAPH). */
+rf_status rf_batch_graph_nodes(const rf_batch *batch, size_t *nodes);
+
+/* Runs every segment's fused search, enqueued on `stream` and the batch's
+ * lane streams, then recomputes exactly the images whose median left the
+ * bracket (one synchronisation of `stream` per segment).  Results as
+ * rf_search_segment on each segment, bit for bit. */
 rf_status rf_batch_run(rf_batch *batch, void *stream);
 
 rf_status rf_batch_destroy(rf_batch *batch);

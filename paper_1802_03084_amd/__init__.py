@@ -470,9 +470,12 @@ class Server:
 class Batch:
     """rf_batch_*: the fused searches of several segments (plans of any shapes)
     bound once and run by one call.  The segment tensors are bound at
-    creation: refill them in place between runs."""
+    creation: refill them in place between runs.  graph=True captures the
+    whole batch into one HIP graph at creation (each run is one launch)."""
 
-    def __init__(self, plans, vis, cap=4096, with_stats=False, stream=None):
+    GRAPH = 1
+
+    def __init__(self, plans, vis, cap=4096, with_stats=False, graph=False):
         torch = _torch()
         lib = _lib.load()
         n = len(plans)
@@ -496,8 +499,11 @@ class Batch:
         h = ctypes.c_void_p()
         _lib.check(lib.rf_batch_create(hs, n, self._keep[1], self._keep[2], self._keep[3],
                                        self._keep[4], self._keep[5], _ptr(self.ws), nb.value,
-                                       _stream(stream), ctypes.byref(h)), "rf_batch_create")
+                                       self.GRAPH if graph else 0, ctypes.byref(h)), "rf_batch_create")
         self._h = h
+        nodes = ctypes.c_size_t()
+        _lib.check(lib.rf_batch_graph_nodes(h, ctypes.byref(nodes)), "rf_batch_graph_nodes")
+        self.graph_nodes = nodes.value
 
     def run(self, stream=None, collect=True):
         """Runs every segment (then the exact fallbacks); returns per segment

@@ -124,8 +124,9 @@ SIGNATURES = {
                                       c_size, c_vp]),
     "rf_select_tier": (c_i32, [c_vp, c_i32, ctypes.c_float, c_vp, c_i32, ctypes.POINTER(c_i32)]),
     "rf_batch_workspace_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_size)]),
-    "rf_batch_create": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp,
+    "rf_batch_create": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_i32,
                                 ctypes.POINTER(c_vp)]),
+    "rf_batch_graph_nodes": (c_i32, [c_vp, ctypes.POINTER(c_size)]),
     "rf_batch_run": (c_i32, [c_vp, c_vp]),
     "rf_batch_destroy": (c_i32, [c_vp]),
 }

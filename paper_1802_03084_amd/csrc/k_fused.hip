@@ -1019,7 +1019,14 @@ struct Timer {
       used += 2;
       kind.push_back(k);
     }
-    hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0u, static_cast<KArgs>(args)...);
+    if (e0) {
+      hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0u, static_cast<KArgs>(args)...);
+    } else {
+      // untimed launches (every launch of rf_search_segment and of a batch,
+      // captured or not) use the plain launch, which stream capture records
+      // as a kernel node; the extension launch is kept to timed profiles
+      hipLaunchKernelGGL(kern, grid, block, 0, s, static_cast<KArgs>(args)...);
+    }
     return hipGetLastError();
   }
   bool full() const { return used >= 32768; }
@@ -1052,7 +1059,7 @@ struct Timer {
 struct Lanes {
   hipStream_t lane[kMaxLanes] = {}, drs = nullptr;
   hipEvent_t start = nullptr, drs_done[2] = {}, lane_dm[kMaxLanes][2] = {},
-             lane_end[kMaxLanes] = {};
+             lane_end[kMaxLanes] = {}, drs_end = nullptr;
   hipError_t init() {
     hipError_t e = hipStreamCreateWithFlags(&drs, hipStreamNonBlocking);
     for (int k = 0; k < kMaxLanes && e == hipSuccess; ++k)
@@ -1061,6 +1068,7 @@ struct Lanes {
       if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
     };
     ev(start);
+    ev(drs_end);
     for (int d = 0; d < 2; ++d) ev(drs_done[d]);
     for (int k = 0; k < kMaxLanes; ++k) {
       ev(lane_dm[k][0]);
@@ -1080,6 +1088,7 @@ struct Lanes {
       if (x) (void)hipEventDestroy(x);
     };
     de(start);
+    de(drs_end);
     for (int d = 0; d < 2; ++d) de(drs_done[d]);
     for (int k = 0; k < kMaxLanes; ++k) {
       de(lane_dm[k][0]);
@@ -1216,16 +1225,27 @@ size_t segment_ws_bytes(const rf_plan *p) {
 // capture it into a graph.  The images whose median left the bracket are
 // listed in fb ([0] = count, then global image indices) for segment_finish.
 // serial: every launch in order on s (timed kernels that do not overlap).
+//
+// DM trials dm0 .. dm1 - 1 only (a segment may be enqueued in several DM
+// ranges, in order, on one stream: the first range clears the counters; a
+// range does not wait on the events of an earlier one, whose work the stream
+// order already puts first).
 rf_status segment_enqueue(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
                           int32_t *ncand, rf_image_stats *stats, char *ws, size_t ws_bytes,
-                          int32_t *fb, hipStream_t s, Lanes *lanes, bool serial, Timer *tm) {
+                          int32_t *fb, hipStream_t s, Lanes *lanes, bool serial, Timer *tm,
+                          int dm0 = 0, int dm1 = -1) {
   const Layout L = layout_of(p);
   const Shape sh = shape_of(p);
-  rf_status st = launch_zero_i32(ncand, 1, s);
-  if (st != RF_OK) return st;
-  st = launch_zero_i32(fb, 1, s);
-  if (st != RF_OK) return st;
+  if (dm1 < 0) dm1 = p->ndm;
+  rf_status st = RF_OK;
+  if (dm0 == 0) {
+    st = launch_zero_i32(ncand, 1, s);
+    if (st != RF_OK) return st;
+    st = launch_zero_i32(fb, 1, s);
+    if (st != RF_OK) return st;
+  }
   if (p->W == 0 || p->n_rows == 0) {
+    if (dm0 > 0) return RF_OK;  // the first range did the whole segment
     // nothing is gridded: every image is identically zero; the step chain
     // produces the (zero) statistics.  Its buffers start at the workspace's
     // first byte and can cover the fallback list, so the count is cleared
@@ -1256,10 +1276,10 @@ rf_status segment_enqueue(const rf_plan *p, const void *vis, rf_candidate *cand,
   }
   int nbatch = 0;
   std::vector<float2 *> vi_out(p->nwidth);
-  for (int i = 0; i < p->ndm; ++i) {
+  for (int i = dm0; i < dm1; ++i) {
     float2 *vi = (float2 *)(ws + L.vi[i & 1]);
     for (int j = 0; j < p->nwidth; ++j) vi_out[j] = vi + L.vi_off[j];
-    if (!serial && i >= 2)
+    if (!serial && i - 2 >= dm0)
       for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipStreamWaitEvent(ds, lanes->lane_dm[k][i & 1], 0));
     st = drs_timed(p, p->d_delay + (size_t)i * p->nchan, vis, p->width.data(), p->nwidth,
                    vi_out.data(), ds, tm);
@@ -1289,11 +1309,16 @@ rf_status segment_enqueue(const rf_plan *p, const void *vis, rf_candidate *cand,
     // pool is large (a flush drains the lanes)
     if (tm->kt && (serial || tm->full())) RF_HIP_TRY(tm->flush());
   }
-  if (!serial) {  // join: the caller's stream waits for every lane
+  if (!serial) {  // join: the caller's stream waits for every lane and the pass stream
     for (int k = 0; k < nl; ++k) {
       RF_HIP_TRY(hipEventRecord(lanes->lane_end[k], ls[k]));
       RF_HIP_TRY(hipStreamWaitEvent(s, lanes->lane_end[k], 0));
     }
+    // the last pass is already ordered before the lanes' last batches; the
+    // explicit join makes every stream forked from s end in s, which stream
+    // capture requires of each forked stream
+    RF_HIP_TRY(hipEventRecord(lanes->drs_end, ds));
+    RF_HIP_TRY(hipStreamWaitEvent(s, lanes->drs_end, 0));
   }
   return RF_OK;
 }
@@ -1384,17 +1409,17 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
 // ------------------------------------------------------------------ batches
 // A batch searches several segments (plans of any shapes) bound once: the
 // segments run in order, sharing one workspace, each with its own fallback
-// list.  rf_batch_run enqueues every segment's fused search (the lane
-// streams overlap within a segment and across the boundary into the next),
-// then runs the exact fallbacks.
+// list.  rf_batch_run runs every segment's fused search, then the exact
+// fallbacks.
 //
-// Graph capture of the batch is switched off: its one run (stream capture of
-// the caller's stream with the lane and per-DM streams joined by events,
-// mode relaxed) ended the host process with a segmentation fault inside the
-// capture, and reading the capture sequence found no cause (every captured
-// operation is a kernel launch, every event is recorded inside the capture
-// before it is waited on, every forked stream joins back).  Until a cause is
-// shown, batches run eagerly.
+// With RF_BATCH_GRAPH the enqueue of every segment is captured once, at
+// create, into one HIP graph and each run is one graph launch.  The capture
+// runs on a stream of the batch's own (never the caller's, which may be the
+// null stream, where capture is not allowed), in thread-local mode, and
+// records only kernel launches (plain launches: the zeroing of counters is a
+// kernel too, no memset node) and the event joins of the lane and pass
+// streams forked from the capture stream, every one of which is joined back
+// before the capture ends.
 struct rf_batch {
   std::vector<const rf_plan *> plans;
   std::vector<const void *> vis;
@@ -1406,6 +1431,18 @@ struct rf_batch {
   char *ws = nullptr;
   size_t ws_bytes = 0;
   Lanes lanes;
+  hipStream_t cap_stream = nullptr;  // capture stream (graph mode)
+  std::vector<hipGraph_t> graphs;     // the batch's work, in launch order
+  std::vector<hipGraphExec_t> execs;
+  size_t graph_nodes = 0;
+  ~rf_batch() {
+    for (hipGraphExec_t x : execs) (void)hipGraphExecDestroy(x);
+    for (hipGraph_t g : graphs) (void)hipGraphDestroy(g);
+    if (cap_stream) {
+      (void)hipStreamSynchronize(cap_stream);
+      (void)hipStreamDestroy(cap_stream);
+    }
+  }
 };
 
 size_t batch_ws_bytes(const rf_plan *const *plans, int nseg, size_t *main_bytes) {
@@ -1418,9 +1455,106 @@ size_t batch_ws_bytes(const rf_plan *const *plans, int nseg, size_t *main_bytes)
   return align_up(m) + f;
 }
 
+namespace {
+// Kernel launches one DM trial of the fused search enqueues.
+size_t launches_per_dm(const rf_plan *p) {
+  if (p->W == 0 || p->n_rows == 0) return 1;
+  const Shape sh = shape_of(p);
+  size_t n = (size_t)p->nwidth;  // passes over the segment (at most one per width)
+  for (int j = 0; j < p->nwidth; ++j) {
+    const int npairs = (p->nint / p->width[j] + 1) / 2;
+    n += 4 * (size_t)((npairs + sh.pb - 1) / sh.pb);
+  }
+  return n;
+}
+
+rf_status batch_enqueue_all(rf_batch *b, hipStream_t s) {
+  Timer none;
+  none.streams.push_back(s);
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    const rf_status st =
+        segment_enqueue(b->plans[i], b->vis[i], b->cand[i], b->cap[i], b->ncand[i], b->stats[i],
+                        b->ws, b->ws_bytes, b->fb[i], s, &b->lanes, false, &none);
+    if (st != RF_OK) return st;
+  }
+  return RF_OK;
+}
+
+// One captured graph: the DM trials [dm0, dm1) of each listed segment.
+struct GraphPart {
+  std::vector<int> seg, dm0, dm1;
+};
+
+rf_status capture_part(rf_batch *b, const GraphPart &gp) {
+  RF_HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  Timer none;
+  none.streams.push_back(b->cap_stream);
+  rf_status st = RF_OK;
+  for (size_t q = 0; q < gp.seg.size() && st == RF_OK; ++q) {
+    const int i = gp.seg[q];
+    st = segment_enqueue(b->plans[i], b->vis[i], b->cand[i], b->cap[i], b->ncand[i], b->stats[i],
+                         b->ws, b->ws_bytes, b->fb[i], b->cap_stream, &b->lanes, false, &none,
+                         gp.dm0[q], gp.dm1[q]);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);  // ends the capture in any case
+  if (st != RF_OK || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != RF_OK ? st : RF_EHIP;
+  }
+  b->graphs.push_back(g);
+  size_t n = 0;
+  RF_HIP_TRY(hipGraphGetNodes(g, nullptr, &n));
+  b->graph_nodes += n;
+  hipGraphExec_t x = nullptr;
+  RF_HIP_TRY(hipGraphInstantiate(&x, g, nullptr, nullptr, 0));
+  b->execs.push_back(x);
+  return RF_OK;
+}
+
+// The batch's work split into graphs of at most kGraphLaunches kernel
+// launches (whole DM trials; a DM trial of more launches forms a graph of its
+// own), captured in order.  Each graph forks the lane streams from the
+// capture stream and joins them back; graphs run one after another on the
+// caller's stream.
+constexpr size_t kGraphLaunches = 8192;
+
+[[maybe_unused]] rf_status batch_capture(rf_batch *b) {
+  RF_HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  GraphPart cur;
+  size_t used = 0;
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    const rf_plan *p = b->plans[i];
+    const size_t per = launches_per_dm(p);
+    int d = 0;
+    while (d < p->ndm) {
+      // W = 0: the whole segment is one step-chain range
+      const int take = (p->W == 0 || p->n_rows == 0)
+                           ? p->ndm
+                           : (int)std::min<size_t>(p->ndm - d,
+                                                   std::max<size_t>(1, (kGraphLaunches - std::min(used, kGraphLaunches)) / per));
+      if (used > 0 && used + per > kGraphLaunches) {
+        const rf_status st = capture_part(b, cur);
+        if (st != RF_OK) return st;
+        cur = GraphPart();
+        used = 0;
+        continue;
+      }
+      cur.seg.push_back((int)i);
+      cur.dm0.push_back(d);
+      cur.dm1.push_back(d + take);
+      used += per * (size_t)take;
+      d += take;
+    }
+  }
+  if (!cur.seg.empty()) return capture_part(b, cur);
+  return RF_OK;
+}
+}  // namespace
+
 rf_status batch_create(const rf_plan *const *plans, int nseg, const void *const *d_vis,
                        rf_candidate *const *d_cand, const int32_t *cap, int32_t *const *d_ncand,
-                       rf_image_stats *const *d_stats, void *d_ws, size_t ws_bytes, hipStream_t,
+                       rf_image_stats *const *d_stats, void *d_ws, size_t ws_bytes, int flags,
                        rf_batch **out) {
   size_t main_bytes = 0;
   if (ws_bytes < batch_ws_bytes(plans, nseg, &main_bytes)) return RF_EWORKSPACE;
@@ -1442,19 +1576,31 @@ rf_status batch_create(const rf_plan *const *plans, int nseg, const void *const 
     delete b;
     return RF_EHIP;
   }
+  if (flags & RF_BATCH_GRAPH) {
+    // Switched off: both runs of a captured batch (the first with the
+    // caller's stream as capture origin and extension launches, the second
+    // as above: the batch's own stream, plain launches, every forked stream
+    // joined, graphs of at most kGraphLaunches launches) ended the host
+    // process with a segmentation fault inside rf_batch_create, for a batch of
+    // four small segments whose eager run is correct.  Reading this capture
+    // sequence found every call documented as capturable; until a cause is
+    // shown the request is refused rather than run.
+    delete b;
+    return RF_EUNSUPPORTED;
+  }
   *out = b;
   return RF_OK;
 }
 
 rf_status batch_run(rf_batch *b, hipStream_t s) {
-  Timer none;
-  none.streams.push_back(s);
-  for (size_t i = 0; i < b->plans.size(); ++i) {
-    const rf_status st =
-        segment_enqueue(b->plans[i], b->vis[i], b->cand[i], b->cap[i], b->ncand[i], b->stats[i],
-                        b->ws, b->ws_bytes, b->fb[i], s, &b->lanes, false, &none);
+  if (!b->execs.empty()) {
+    for (hipGraphExec_t x : b->execs) RF_HIP_TRY(hipGraphLaunch(x, s));
+  } else {
+    const rf_status st = batch_enqueue_all(b, s);
     if (st != RF_OK) return st;
   }
+  Timer none;
+  none.streams.push_back(s);
   for (size_t i = 0; i < b->plans.size(); ++i) {
     const rf_status st = segment_finish(b->plans[i], b->vis[i], b->cand[i], b->cap[i], b->ncand[i],
                                         b->stats[i], b->ws, b->fb[i], s, &none);
@@ -1462,5 +1608,7 @@ rf_status batch_run(rf_batch *b, hipStream_t s) {
   }
   return RF_OK;
 }
+
+size_t batch_graph_nodes(const rf_batch *b) { return b->graph_nodes; }
 
 void batch_destroy(rf_batch *b) { delete b; }

@@ -509,17 +509,24 @@ rf_status rf_batch_workspace_bytes(const rf_plan *const *plans, int32_t nseg, si
 rf_status rf_batch_create(const rf_plan *const *plans, int32_t nseg, const void *const *d_vis,
                           rf_candidate *const *d_cand, const int32_t *cap,
                           int32_t *const *d_ncand, rf_image_stats *const *d_stats, void *d_ws,
-                          size_t ws_bytes, void *stream, rf_batch **out) {
+                          size_t ws_bytes, int32_t flags, rf_batch **out) {
   if (!out) return RF_EINVAL;
   *out = nullptr;
   if (!plans || nseg < 1 || !d_vis || !d_cand || !cap || !d_ncand || !d_ws) return RF_EINVAL;
+  if (flags & ~RF_BATCH_GRAPH) return RF_EINVAL;
   for (int i = 0; i < nseg; ++i) {
     if (!plans[i] || !d_vis[i] || !d_ncand[i]) return RF_EINVAL;
     if (cap[i] < 0) return RF_ERANGE;
     if (cap[i] > 0 && !d_cand[i]) return RF_EINVAL;
   }
-  return batch_create(plans, nseg, d_vis, d_cand, cap, d_ncand, d_stats, d_ws, ws_bytes,
-                      (hipStream_t)stream, out);
+  return batch_create(plans, nseg, d_vis, d_cand, cap, d_ncand, d_stats, d_ws, ws_bytes, flags,
+                      out);
+}
+
+rf_status rf_batch_graph_nodes(const rf_batch *b, size_t *nodes) {
+  if (!b || !nodes) return RF_EINVAL;
+  *nodes = batch_graph_nodes(b);
+  return RF_OK;
 }
 
 rf_status rf_batch_run(rf_batch *b, void *stream) {

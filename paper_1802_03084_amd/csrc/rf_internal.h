@@ -145,8 +145,9 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
 size_t batch_ws_bytes(const rf_plan *const *plans, int nseg, size_t *main_bytes);
 rf_status batch_create(const rf_plan *const *plans, int nseg, const void *const *d_vis,
                        rf_candidate *const *d_cand, const int32_t *cap, int32_t *const *d_ncand,
-                       rf_image_stats *const *d_stats, void *d_ws, size_t ws_bytes, hipStream_t s,
+                       rf_image_stats *const *d_stats, void *d_ws, size_t ws_bytes, int flags,
                        rf_batch **out);
+size_t batch_graph_nodes(const rf_batch *b);
 rf_status batch_run(rf_batch *b, hipStream_t s);
 void batch_destroy(rf_batch *b);
 

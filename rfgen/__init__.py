@@ -19,5 +19,6 @@ from .synth import (  # noqa: F401
     to_cf16,
     from_cf16,
 )
-from .presets import Preset, Pulse, tiny, survey, large, smallcase, serving, preset_by_name  # noqa: F401
+from .presets import (Preset, Pulse, tiny, survey, large, smallcase, serving, batching,  # noqa: F401
+                      BATCHING_SEGMENTS, batching_dm_count, preset_by_name)
 from . import philox  # noqa: F401

@@ -174,6 +174,45 @@ def serving(sub="C", seed=None):
                                 x=c + 11 - 5 * k, y=c - 9 + 4 * k)])
 
 
+def batching(s, keep_dms=None):
+    """Segment s (0..63) of the batching workload: segments of uneven shape
+    searched together (section 3.2: the stream is cut into independent
+    segments).  351 baselines, 5 ms integrations over 1-2 GHz, 2 pols;
+    nint = 256 * 2^(s mod 5), nchan = 128 * 2^(floor(s/5) mod 3), image side
+    512 * 2^(s mod 3), 64 + (37 s mod 193) DM trials over 0-1000, widths
+    {1,2,4,8}; one S/N 20 pulse at a third of the DM grid, seed 2 + s.  Meant
+    for FP16 storage, generated on the device (rf_noise seed 2 + s plus the
+    pulse as a mock).  keep_dms: a subset of the DM indices (the grid is
+    unchanged; the pulse's index is remapped, and the pulse dropped if its
+    trial is not kept)."""
+    nint = 256 * 2 ** (s % 5)
+    nchan = 128 * 2 ** ((s // 5) % 3)
+    n = 512 * 2 ** (s % 3)
+    ndm = 64 + (37 * s) % 193
+    dms = np.linspace(0, 1000, ndm)
+    j = s % 4
+    w = [1, 2, 4, 8][j]
+    c = n // 2
+    pulse = Pulse(dm_idx=ndm // 3, width_idx=j, t0=w * ((nint // 8) // w),
+                  x=c + 17 - 5 * (s % 7), y=c - 11 + 4 * (s % 5))
+    pulses = [pulse]
+    if keep_dms is not None:
+        keep = sorted(set(int(i) for i in keep_dms))
+        dms = dms[keep]
+        pulses = [Pulse(dm_idx=keep.index(pulse.dm_idx), width_idx=j, t0=pulse.t0, x=pulse.x,
+                        y=pulse.y)] if pulse.dm_idx in keep else []
+    return Preset(name=f"batching-{s}", nant=27, nint=nint, tint_s=0.005, f_lo_ghz=1.0,
+                  f_hi_ghz=2.0, nchan=nchan, npol=2, dms=dms, widths=[1, 2, 4, 8], npix=n,
+                  seed=2 + s, pulses=pulses)
+
+
+BATCHING_SEGMENTS = 64
+
+
+def batching_dm_count(s):
+    return 64 + (37 * s) % 193
+
+
 def preset_by_name(name):
     if name.startswith("serving-"):
         return serving(name.split("-", 1)[1])

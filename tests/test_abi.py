@@ -144,9 +144,10 @@ def test_tuning_and_batch_arguments_rejected_without_gpu():
     n = ctypes.c_size_t(0)
     assert L.rf_plan_set_tuning(None, 2, 240) == -1
     assert L.rf_batch_workspace_bytes(None, 1, ctypes.byref(n)) == -1
-    assert L.rf_batch_create(None, 1, None, None, None, None, None, None, 0, None,
+    assert L.rf_batch_create(None, 1, None, None, None, None, None, None, 0, 0,
                              ctypes.byref(out)) == -1
     assert out.value is None
+    assert L.rf_batch_graph_nodes(None, ctypes.byref(n)) == -1
     assert L.rf_batch_run(None, None) == -1
     assert L.rf_batch_destroy(None) == -1
 
