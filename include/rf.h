@@ -204,6 +204,23 @@ rf_status rf_image(const rf_plan *plan, const void *d_grid, int32_t nimg, float 
                    void *d_ws, size_t ws_bytes, void *stream);
 
 /*
+ * rf_image_static: rf_image for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same kernels and results as rf_image, bit for bit, but
+ * the scratch between the row and column passes is a fixed array of the
+ * library on each GPU (rf_image_static_max_bytes: 64 MiB, held until the
+ * process ends) instead of a workspace argument; nothing is allocated.  The
+ * call needs image_ws = ceil(nimg / 2) * rows * N * 8 bytes of it (rows: the
+ * plan's n_rows): up to 16 images of 1024^2, 4 of 2048^2; larger nimg is
+ * rejected with RF_EWORKSPACE.  Calls on one GPU share the array: calls
+ * that overlap in time on that GPU (other streams, other threads) race.
+ * RF_EINVAL on NULL, RF_ERANGE if nimg < 0; asynchronous on `stream`.
+ */
+rf_status rf_image_static(const rf_plan *plan, const void *d_grid, int32_t nimg, float *d_img,
+                          void *stream);
+rf_status rf_image_static_max_bytes(size_t *bytes);
+
+/*
  * rf_search (section 3.1: threshold each image on S/N):
  * per image, peak = signed max (ties: lowest y*N + x), sigma = 1.4826 *
  * lower median of |img| (exact order statistic of rank floor((N*N-1)/2)),

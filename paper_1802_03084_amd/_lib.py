@@ -102,6 +102,8 @@ SIGNATURES = {
     "rf_resample": (c_i32, [c_vp, c_i32, c_vp, c_i32, c_vp, c_vp]),
     "rf_grid": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp]),
     "rf_image": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_size, c_vp]),
+    "rf_image_static": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp]),
+    "rf_image_static_max_bytes": (c_i32, [ctypes.POINTER(c_size)]),
     "rf_search": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_size, c_vp]),
     "rf_search_segment": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_size, c_vp]),
     "rf_search_segment_steps": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_size, c_vp]),
