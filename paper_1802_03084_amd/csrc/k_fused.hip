@@ -53,17 +53,33 @@ struct WidthSet {
   int nw;
 };
 
+constexpr int kMaxColWaves = 8;  // waves of a column workgroup, at most
+
 struct ColPart {   // per (image, column workgroup)
   float maxv;
   int32_t maxi;
   uint32_t cnt_lo;  // pixels with |value| below the bracket
-  uint32_t n;       // pixels inside the bracket (values kept: min(n, region capacity))
   float lo, hi;     // the bracket [lo, hi) (identical in every workgroup of a pair)
+  // pixels inside the bracket found by each wave of the workgroup; wave w
+  // keeps min(nw[w], capb / waves) of their values in its part of the tile's
+  // list region (values beyond it send the image to the exact fallback)
+  uint32_t nw[kMaxColWaves];
 };
 
 __device__ __forceinline__ bool better(float v, int i, float bv, int bi) {
   return v > bv || (v == bv && i < bi);
 }
+
+// Cross-lane exchange with lane ^ o (o < 64): one ds_bpermute on the byte
+// address ((lane ^ o) << 2), which every exchange at the same o shares.
+__device__ __forceinline__ int xaddr(int o) {
+  return (int)((__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)) ^ (uint32_t)o)
+               << 2);
+}
+__device__ __forceinline__ float xshfl(float v, int addr) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ int xshfl(int v, int addr) { return __builtin_amdgcn_ds_bpermute(addr, v); }
 
 // ------------------------------------------------------------------ drs
 __device__ __forceinline__ void load_pols(const float2 *vis, size_t e, int P, float2 &a,
@@ -334,9 +350,10 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
   }
   // the energy terms: a wave sum per image, then one LDS atomic per wave
 #pragma unroll
-  for (int q = 0; q < 2 * PBW; ++q) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const int ad = xaddr(o);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) e_acc[q] += __shfl_xor(e_acc[q], o, 64);
+    for (int q = 0; q < 2 * PBW; ++q) e_acc[q] += xshfl(e_acc[q], ad);
   }
   if ((tid & 63) == 0) {
 #pragma unroll
@@ -382,12 +399,13 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
   constexpr int NW = NT / 64;
   constexpr int EPT = ((N / 2 + 1) * 2 + NT - 1) / NT;  // energy terms per thread, at most
   static_assert(NT % 2 == 0, "energy terms alternate a, b by thread parity");
+  static_assert(NW <= kMaxColWaves, "per-wave counts of a record");
   __shared__ float2 buf[COLS * S];
   __shared__ float s_e[2][NW];
-  __shared__ uint32_t s_cnt[2];
   __shared__ float w_v[2][NW];
   __shared__ int32_t w_i[2][NW];
   __shared__ uint32_t w_c[2][NW];
+  __shared__ uint32_t w_n[2][NW];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int total = pbn * CB;
   const int per = (total + 7) >> 3;  // tiles per XCD
@@ -421,10 +439,9 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
   }
   fft_first_dft<Sh, COLS, NT>(x);
 #pragma unroll
-  for (int o = 2; o < 64; o <<= 1) e += __shfl_xor(e, o, 64);
+  for (int o = 2; o < 64; o <<= 1) e += xshfl(e, xaddr(o));
   fft_first_store<Sh, COLS, NT, S, false, true>(buf, tw, tid, x);
   if (lane < 2) s_e[lane][wid] = e;
-  if (tid < 2) s_cnt[tid] = 0;
   __syncthreads();
   float ea = 0.f, eb = 0.f;
 #pragma unroll
@@ -437,15 +454,20 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
   const float lo_b = mb * (1.0f - bracket_of<N>()), hi_b = mb * (1.0f + bracket_of<N>());
   const bool hasb = 2 * (p0 + pl) + 1 < nimg_w;
   const int x0 = cb * COLS;
-  // the brackets as bit patterns: [lo, hi) is u - ulo < uwid (unsigned)
-  const uint32_t ulo_a = __float_as_uint(lo_a), uwid_a = __float_as_uint(hi_a) - ulo_a;
-  const uint32_t ulo_b = __float_as_uint(lo_b), uwid_b = __float_as_uint(hi_b) - ulo_b;
-  // this tile's list regions (capb values each) for the two images
-  const auto rla = buf_rsrc(list + ((size_t)(2 * pl) * CB + cb) * capb, (uint32_t)capb * 4u);
-  const auto rlb = buf_rsrc(list + ((size_t)(2 * pl + 1) * CB + cb) * capb, (uint32_t)capb * 4u);
+  // This wave's part of the tile's list regions (capb values per image): capw
+  // values from wid * capw, filled in order by a wave-uniform running count.
+  // (The wave index is made explicitly uniform so that the buffer resources
+  // live in scalar registers.)
+  const int capw = capb / NW;
+  const int uwid = __builtin_amdgcn_readfirstlane(wid);
+  const auto rla = buf_rsrc(list + ((size_t)(2 * pl) * CB + cb) * capb + uwid * capw,
+                            (uint32_t)capw * 4u);
+  const auto rlb = buf_rsrc(list + ((size_t)(2 * pl + 1) * CB + cb) * capb + uwid * capw,
+                            (uint32_t)capw * 4u);
   float bva = -__builtin_inff(), bvb = -__builtin_inff();
   int bia = 0x7fffffff, bib = 0x7fffffff;
-  uint32_t ca = 0, cbn = 0;
+  uint32_t ca = 0, cbn = 0;  // wave-uniform: pixels below the bracket
+  uint32_t na = 0, nb = 0;   // wave-uniform: bracket members found so far
   fft_rest_blocks<Sh, COLS, NT, S, false, true>(buf, tw, tid, [&](int f, int k0, int ks, auto &v) {
     constexpr int R = sizeof(v) / sizeof(v[0]);
     // Image b is computed even when the pair has no second image: its values
@@ -479,64 +501,43 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
         bib = ib;
       }
     }
-    float aa[R], ab[R];
-    uint64_t ba[R], bb[R];  // wave masks of bracket members, per output row
+    // The median bracket, per output row of the wave: the count below it (a
+    // popcount of one ballot) and its members, |p| in [lo, hi) (a second
+    // ballot, less the first), written to this wave's list part at the
+    // running count plus the members in lower lanes.  Slots at or past capw
+    // fall outside the buffer resource and are dropped by the hardware (the
+    // count still grows, which sends the image to the exact fallback).  NaN
+    // pixels are neither below nor inside the bracket.  The list holds the
+    // signed pixel values; the select ranks their magnitudes.
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const float pa = v[r].x, pb = v[r].y;
-      aa[r] = fabsf(pa);
-      ab[r] = fabsf(pb);
-      // wave-uniform count below the bracket; members by one unsigned compare
-      ca += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(aa[r] < lo_a));
-      cbn += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(ab[r] < lo_b));
-      ba[r] = __builtin_amdgcn_ballot_w64(__float_as_uint(aa[r]) - ulo_a < uwid_a);
-      bb[r] = __builtin_amdgcn_ballot_w64(__float_as_uint(ab[r]) - ulo_b < uwid_b);
-    }
-    // Compact the members into the list regions: one LDS reservation per
-    // wave and image; a member's slot is the reservation plus the members
-    // before it (earlier rows, then lower lanes).  Slots at or past capb fall
-    // outside the buffer resource and are dropped by the hardware.  Membership
-    // is tested on the bit patterns (for values >= 0 the integer order is the
-    // float order, NaN included: it lies above every bound).
-    uint32_t na = 0, nb = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      na += (uint32_t)__popcll(ba[r]);
-      nb += (uint32_t)__popcll(bb[r]);
-    }
-    if (na | nb) {
-      uint32_t base = 0;
-      if (lane == 0) {
-        const uint32_t x = na ? atomicAdd(&s_cnt[0], na) : 0u;
-        const uint32_t y = nb ? atomicAdd(&s_cnt[1], nb) : 0u;
-        base = x | (y << 16);  // both below 2^16: a tile holds COLS N <= 8192 pixels
+      // ballots of the plain compares (one VALU compare each); the member
+      // masks by scalar arithmetic
+      const bool a_lo = fabsf(pa) < lo_a, a_hi = fabsf(pa) < hi_a;
+      const bool b_lo = fabsf(pb) < lo_b, b_hi = fabsf(pb) < hi_b;
+      const uint64_t la = __builtin_amdgcn_ballot_w64(a_lo), lb = __builtin_amdgcn_ballot_w64(b_lo);
+      const uint64_t ia = __builtin_amdgcn_ballot_w64(a_hi) & ~la;
+      const uint64_t ib = __builtin_amdgcn_ballot_w64(b_hi) & ~lb;
+      ca += (uint32_t)__popcll(la);
+      cbn += (uint32_t)__popcll(lb);
+      if (ia) {
+        if (a_hi && !a_lo) {
+          const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(ia >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ia, 0u));
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(pa), rla, (int)((na + below) * 4u),
+                                                0, 0);
+        }
+        na += (uint32_t)__popcll(ia);
       }
-      base = __builtin_amdgcn_readfirstlane(base);
-      uint32_t oa = base & 0xffffu, ob = base >> 16;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (ba[r]) {
-          const uint32_t below =
-              __builtin_amdgcn_mbcnt_hi((uint32_t)(ba[r] >> 32),
-                                        __builtin_amdgcn_mbcnt_lo((uint32_t)ba[r], 0u));
-          const uint32_t u = __float_as_uint(aa[r]);
-          __builtin_amdgcn_raw_buffer_store_b32(u, rla,
-                                                u - ulo_a < uwid_a ? (int)((oa + below) * 4u)
-                                                                   : (int)kNoLoad,
+      if (ib) {
+        if (b_hi && !b_lo) {
+          const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(ib >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ib, 0u));
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(pb), rlb, (int)((nb + below) * 4u),
                                                 0, 0);
-          oa += (uint32_t)__popcll(ba[r]);
         }
-        if (bb[r]) {
-          const uint32_t below =
-              __builtin_amdgcn_mbcnt_hi((uint32_t)(bb[r] >> 32),
-                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bb[r], 0u));
-          const uint32_t u = __float_as_uint(ab[r]);
-          __builtin_amdgcn_raw_buffer_store_b32(u, rlb,
-                                                u - ulo_b < uwid_b ? (int)((ob + below) * 4u)
-                                                                   : (int)kNoLoad,
-                                                0, 0);
-          ob += (uint32_t)__popcll(bb[r]);
-        }
+        nb += (uint32_t)__popcll(ib);
       }
     }
   });
@@ -544,8 +545,9 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
   // over the wave and then the workgroup's waves.
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    const float ova = __shfl_xor(bva, o, 64), ovb = __shfl_xor(bvb, o, 64);
-    const int oia = __shfl_xor(bia, o, 64), oib = __shfl_xor(bib, o, 64);
+    const int ad = xaddr(o);
+    const float ova = xshfl(bva, ad), ovb = xshfl(bvb, ad);
+    const int oia = xshfl(bia, ad), oib = xshfl(bib, ad);
     if (better(ova, oia, bva, bia)) {
       bva = ova;
       bia = oia;
@@ -562,6 +564,8 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
     w_i[1][wid] = bib;
     w_c[0][wid] = ca;
     w_c[1][wid] = cbn;
+    w_n[0][wid] = na;
+    w_n[1][wid] = nb;
   }
   __syncthreads();
   if (tid < 2 && (tid == 0 || hasb)) {
@@ -579,9 +583,10 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
     cp.maxv = pk;
     cp.maxi = i;
     cp.cnt_lo = c;
-    cp.n = s_cnt[tid];
     cp.lo = tid == 0 ? lo_a : lo_b;
     cp.hi = tid == 0 ? hi_a : hi_b;
+#pragma unroll
+    for (int w = 0; w < kMaxColWaves; ++w) cp.nw[w] = w < NW ? w_n[tid][w] : 0u;
     part[(size_t)(2 * pl + tid) * CB + cb] = cp;
   }
 }
@@ -637,17 +642,23 @@ constexpr int kMaxCB = 512;       // column workgroups per image, at most
 constexpr int kLdsVals = 20480;   // bracket values staged in LDS (80 KB)
 
 // Per image: combines the column workgroups' records (peak, count below the
-// bracket, bracket counts), stages every kept bracket value in LDS, and finds
-// the median |value| among them.  Images whose median is not inside the
-// bracket, or whose bracket values did not all fit, go to the exact fallback.
-template <int VPR>  // values of each list region loaded up front (64 or 128)
+// bracket, per-wave bracket counts), stages every kept bracket magnitude in
+// LDS, and finds the median |value| among them.  Images whose median is not
+// inside the bracket, or whose bracket values did not all fit (a wave's list
+// part or the LDS stage), go to the exact fallback.  The list of column
+// workgroup t is CAPB values: wave w's part from w * CAPW, nw[w] of them used.
+template <int N>
 __global__ __launch_bounds__(kSelThreads) void k_select(
-    const ColPart *__restrict__ part, const float *__restrict__ list, int cbn, int capb,
+    const ColPart *__restrict__ part, const float *__restrict__ list, int cbn,
     int nimg_w, int p0, int pbn, int npix, int dm_idx,
     int width_idx, int width, int64_t stat_base, rf_image_stats *__restrict__ stats,
     rf_candidate *__restrict__ cand, int ncap, int32_t *__restrict__ ncand,
     int32_t *__restrict__ fb_count, int32_t *__restrict__ fb_list, float thr, int t_begin,
     int t_end) {
+  constexpr int CAPB = ColCfg<N>::COLS * N / 16;  // list values per column workgroup
+  constexpr int NWC = ColCfg<N>::NT / 64;         // waves per column workgroup
+  constexpr int CAPW = CAPB / NWC;                // list values per wave
+  static_assert(CAPB % 64 == 0 && CAPW >= 16, "list parts");
   __shared__ uint32_t hist[kBins];
   __shared__ uint32_t wsum[kSelThreads / 64];
   __shared__ uint32_t sel[2];
@@ -659,7 +670,8 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
   __shared__ float s_v;
   __shared__ int32_t s_i;
   __shared__ uint32_t s_lo, s_n, s_of;
-  __shared__ uint32_t r_cnt[kMaxCB], r_off[kMaxCB];
+  __shared__ uint32_t r_off[kMaxCB * NWC];  // LDS offset of (workgroup, wave) values
+  __shared__ uint32_t r_cnt[kMaxCB * NWC];  // and their number
   __shared__ float vals[kLdsVals];
   __shared__ float binv[kBinCap];
   __shared__ uint32_t s_nc;
@@ -670,16 +682,17 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
   if (pl >= pbn || k >= nimg_w) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const ColPart *pp = part + (size_t)il * cbn;
-  {  // combine the column workgroups' records; region r holds r_cnt[r] values
-     // placed at r_off[r] in LDS (kMaxCB / kSelThreads consecutive regions per thread)
+  {  // combine the column workgroups' records; workgroup r's values go to
+     // LDS from r_off[r * NWC] (kMaxCB / kSelThreads consecutive records per thread)
     constexpr int RPT = kMaxCB > kSelThreads ? kMaxCB / kSelThreads : 1;
     float v = -__builtin_inff();
     int32_t i = 0x7fffffff;
-    uint32_t lo = 0, nn = 0, of = 0, cnt[RPT];
+    uint32_t lo = 0, nn = 0, of = 0, cnt[RPT][NWC];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int r = RPT * tid + q;
-      cnt[q] = 0;
+#pragma unroll
+      for (int w = 0; w < NWC; ++w) cnt[q][w] = 0;
       if (r < cbn) {
         const ColPart c = pp[r];
         if (better(c.maxv, c.maxi, v, i)) {
@@ -687,9 +700,12 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
           i = c.maxi;
         }
         lo += c.cnt_lo;
-        cnt[q] = c.n;
-        nn += c.n;
-        of |= c.n > (uint32_t)capb;
+#pragma unroll
+        for (int w = 0; w < NWC; ++w) {
+          cnt[q][w] = c.nw[w];
+          nn += c.nw[w];
+          of |= c.nw[w] > (uint32_t)CAPW;
+        }
       }
     }
     uint32_t inc = nn;  // inclusive scan of the bracket counts over the block
@@ -724,9 +740,12 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
     for (int q = 0; q < RPT; ++q) {
       const int r = RPT * tid + q;
       if (r < cbn) {
-        r_cnt[r] = cnt[q];
-        r_off[r] = at;
-        at += cnt[q];
+#pragma unroll
+        for (int w = 0; w < NWC; ++w) {
+          r_off[r * NWC + w] = at;
+          r_cnt[r * NWC + w] = min(cnt[q][w], (uint32_t)CAPW);
+          at += cnt[q][w];
+        }
       }
     }
     if (tid == 0) {
@@ -756,29 +775,27 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
     med = 0.f;  // identically zero image (every pixel equals the zero peak)
   } else if (!ovf && s_lo <= rank && rank < s_lo + n) {
     uint32_t r = rank - s_lo;
-    // stage the regions in LDS: a wave takes G regions at a time with their
-    // first VPR values' loads all in flight (16 loads per lane; VPR is chosen
-    // above a region's typical count)
-    const float *lr = list + (size_t)il * cbn * capb;
-    constexpr int NWV = kSelThreads / 64, PR = VPR / 64, G = 16 / PR;
-    for (int g0 = wid; g0 < cbn; g0 += NWV * G) {
-      float x[G][PR];
+    // Stage the kept magnitudes in LDS.  The list parts (one per wave of each
+    // column workgroup, CAPW values apart) hold a few values each: 16 lanes
+    // take one part, a wave four parts per load and 64 parts per round with
+    // all 16 loads in flight; values past a part's sixteenth (rare) follow.
+    const float *lr = list + (size_t)il * cbn * CAPB;
+    constexpr int NWV = kSelThreads / 64;
+    const int nparts = cbn * NWC, sub = lane >> 4, sl = lane & 15;
+    for (int g0 = wid * 64; g0 < nparts; g0 += NWV * 64) {
+      float x[16];
 #pragma unroll
-      for (int u = 0; u < G; ++u) {
-        const int rg = min(g0 + u * NWV, cbn - 1);
-        const float *rp = lr + (size_t)rg * capb;
-#pragma unroll
-        for (int h = 0; h < PR; ++h) x[u][h] = rp[lane + 64 * h];
+      for (int u = 0; u < 16; ++u) {
+        const int pt = min(g0 + 4 * u + sub, nparts - 1);
+        x[u] = lr[(size_t)pt * CAPW + sl];
       }
 #pragma unroll
-      for (int u = 0; u < G; ++u) {
-        const int rg = g0 + u * NWV;
-        if (rg < cbn) {
-          const uint32_t c = r_cnt[rg], o = r_off[rg];
-#pragma unroll
-          for (int h = 0; h < PR; ++h)
-            if ((uint32_t)(lane + 64 * h) < c) vals[o + lane + 64 * h] = x[u][h];
-          for (uint32_t e = lane + VPR; e < c; e += 64) vals[o + e] = lr[(size_t)rg * capb + e];
+      for (int u = 0; u < 16; ++u) {
+        const int pt = g0 + 4 * u + sub;
+        if (pt < nparts) {
+          const uint32_t c = r_cnt[pt], o = r_off[pt];
+          if ((uint32_t)sl < c) vals[o + sl] = fabsf(x[u]);
+          for (uint32_t e = 16 + sl; e < c; e += 16) vals[o + e] = fabsf(lr[(size_t)pt * CAPW + e]);
         }
       }
     }
@@ -1131,11 +1148,8 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
   RF_HIP_TRY(tm->launch(RF_K_COLS, k_cols_stats<N>, dim3(cgrid), dim3(ColCfg<N>::NT), s, M,
                         p->n_rows, p->vmax, nimg_w, p0, pbn, inv_w, p->d_tw, epart, p->n_rp, part,
                         list, sh.capb));
-  // a list region holds about COLS N x 0.86% x (bracket half-width in %) values
-  constexpr int per_region = (int)(ColCfg<N>::COLS * N * 0.86f * bracket_of<N>());
-  RF_HIP_TRY(tm->launch(RF_K_SELECT, k_select<(per_region > 48 ? 128 : 64)>, dim3(2 * pbn),
-                        dim3(kSelThreads), s, part, list,
-                        sh.cbp, sh.capb, nimg_w, p0, pbn, N, dm_idx, width_idx, width, stat_base,
+  RF_HIP_TRY(tm->launch(RF_K_SELECT, k_select<N>, dim3(2 * pbn), dim3(kSelThreads), s, part,
+                        list, sh.cbp, nimg_w, p0, pbn, N, dm_idx, width_idx, width, stat_base,
                         stats, cand, cap, ncand, fb, fb + 1, p->threshold, p->t_begin,
                         p->t_end));
   return RF_OK;
