@@ -60,7 +60,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def serving_leg(speedup, nseg, nslots, storage):
+def serving_leg(speedup, nseg, nslots, storage, burst_nseg=0):
     """The serving workload: three subarrays (A 10 antennas 5 ms, B 19
     antennas 10 ms, C 27 antennas 5 ms; 10.24 s segments, 256 channels over
     1.272-1.528 GHz, 64 DMs, widths {1,2,4,8}, 512^2 images) streamed to an
@@ -115,6 +115,9 @@ def serving_leg(speedup, nseg, nslots, storage):
             rows, n, tm = srv.wait(tk)
             out.append((i, rows, n, tm))
             k += 1
+            if k % 30 == 0:
+                log(f"serving: {k}/{len(schedule)} segments done, last latency "
+                    f"{tm['latency_s'] * 1e3:.0f} ms")
         th.join()
         return out, time.perf_counter() - t0
 
@@ -129,8 +132,19 @@ def serving_leg(speedup, nseg, nslots, storage):
         q = subs[i][1].pulses[0]
         keys = {(int(r["dm_idx"]), int(r["width_idx"]), int(r["t_int"]), int(r["x"]), int(r["y"])) for r in rows}
         found += (q.dm_idx, q.width_idx, q.t0, q.x, q.y) in keys
-    burst = [(0.0, i) for j in range(nseg) for i in range(3)]
+    burst = [(0.0, i) for j in range(burst_nseg or nseg) for i in range(3)]
     resb, wall_b = run(burst)
+
+    def overlap(res):
+        """Largest number of requests on the device at once (admitted, not
+        yet done), from the server's own admission and completion times."""
+        ev = sorted([(tm["started_s"], 1) for _, _, _, tm in res] +
+                    [(tm["done_s"], -1) for _, _, _, tm in res], key=lambda e: (e[0], e[1]))
+        cur = best = 0
+        for _, d in ev:
+            cur += d
+            best = max(best, cur)
+        return best
     srv.close()
     imgs = sum(subs[i][2].n_images for i, _, _, _ in resb)
     out = {
@@ -144,9 +158,12 @@ def serving_leg(speedup, nseg, nslots, storage):
                   "latency_max_s": round(float(lat.max()), 4),
                   "per_subarray_p99_s": {subs[i][0]: round(float(np.percentile(
                       [tm["latency_s"] for j, _, _, tm in res if j == i], 99)), 4) for i in range(3)},
-                  "pulses_recovered": f"{found}/{len(res)}"},
+                  "pulses_recovered": f"{found}/{len(res)}",
+                  "max_requests_on_device": overlap(res),
+                  "wall_s": round(wall_p, 1)},
         "burst": {"segments": len(resb), "wall_s": round(wall_b, 3), "images_per_s": round(imgs / wall_b, 1),
-                  "rtf": round(len(resb) / 3 * seg_s / wall_b, 2)},
+                  "rtf": round(len(resb) / 3 * seg_s / wall_b, 2),
+                  "max_requests_on_device": overlap(resb)},
     }
     log(f"serving paced x{speedup}: p50 {out['paced']['latency_p50_s'] * 1e3:.0f} ms, "
         f"p99 {out['paced']['latency_p99_s'] * 1e3:.0f} ms over {len(res)} segments; burst "
@@ -375,6 +392,8 @@ def main():
     ap.add_argument("--serving-segments", type=int, default=12, help="segments per subarray")
     ap.add_argument("--serving-slots", type=int, default=3)
     ap.add_argument("--serving-only", action="store_true", help="run only the serving legs")
+    ap.add_argument("--serving-burst-segments", type=int, default=0,
+                    help="segments per subarray of the burst run (default: as the paced run)")
     ap.add_argument("--no-periodic", action="store_true", help="skip the periodicity-search leg")
     ap.add_argument("--large", type=int, default=0, metavar="NDM",
                     help="only time the large workload (8192 x 1 ms, 1024 chans, 2048^2) over NDM "
@@ -432,7 +451,8 @@ def main():
 
     if args.serving_only:
         print(json.dumps({"serving": serving_leg(args.serving_speedup, args.serving_segments,
-                                                 args.serving_slots, "cf16")}), flush=True)
+                                                 args.serving_slots, "cf16",
+                                                 args.serving_burst_segments)}), flush=True)
         return
 
     p = rfgen.survey() if args.workload == "survey" else rfgen.tiny()

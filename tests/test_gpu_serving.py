@@ -67,13 +67,19 @@ def test_served_in_mix_equals_alone(torch, segments):
     for rep in range(2):
         for i, (p, g, h, _, _) in enumerate(segments):
             tickets.append((i, srv.submit(g, h, cap=4096)))
+    spans = []
     for i, t in tickets:
         rows, n, tm = srv.wait(t)
         _, _, _, rows0, n0 = segments[i]
         assert n == n0, i
         assert np.array_equal(rows, rows0), i
         assert tm["latency_s"] >= 0 and tm["done_s"] >= tm["started_s"] >= tm["released_s"]
+        spans.append((tm["started_s"], tm["done_s"]))
     srv.close()
+    # continuous batching: requests were on the device together (one was
+    # admitted before another had finished)
+    spans.sort()
+    assert any(s2 < d1 for (s1, d1), (s2, d2) in zip(spans, spans[1:])), spans
     p0 = segments[0][0]
     q = p0.pulses[0]
     assert (q.dm_idx, q.width_idx, q.t0, q.x, q.y) in cand_keys(segments[0][3])
