@@ -34,8 +34,10 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X fp32 vector, published
 # copy (FETCH_SIZE reads 524,300 KiB for 1 GiB read: x2; WRITE_SIZE 1,049,000
 # KiB for 1 GiB written: x1).  Valid only for the kernel sources with this
 # digest (k_fused.hip, fft.h, rf_internal.h); null once they change.
-FUSED_TRAFFIC = {"digest": None, "fetch_scale": 2.0, "write_scale": 1.0,
-                 "kib_per_dispatch": {}}
+FUSED_TRAFFIC = {"digest": "07d67b06171ec643", "fetch_scale": 2.0, "write_scale": 1.0,
+                 "kib_per_dispatch": {"drs": (1439094.6, 2696010.2), "grid": (13167.0, 7362.7),
+                                      "rows": (6954.3, 113502.3), "cols": (56793.5, 1976.3),
+                                      "select": (2361.5, 0.0)}}
 
 
 def fused_kernel_digest():
