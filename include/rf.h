@@ -250,11 +250,34 @@ rf_status rf_search(const rf_plan *plan, const float *d_img, int32_t nimg,
  * is set to 0 on the device first.  d_stats (nullable) receives [n_images]
  * stats in (dm_idx, width_idx, k) order.  d_ws: rf_workspace_bytes(
  * RF_OP_SEGMENT).  Synchronises `stream` once before returning (to learn
- * whether any image needs the exact recomputation).
+ * whether any image needs the exact recomputation); that recomputation is
+ * enqueued on `stream` after it, so the results are complete in `stream`
+ * order, not necessarily when the call returns.
  */
 rf_status rf_search_segment(const rf_plan *plan, const void *d_vis, rf_candidate *d_cand,
                             int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,
                             void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * rf_search_segment in two calls, for callers that must not block while the
+ * search runs.  rf_search_segment_begin checks the arguments as
+ * rf_search_segment does, enqueues the fused search on `stream` (and lane
+ * streams of its own, joined back to `stream`) and returns at once with a job;
+ * nothing is enqueued on error (*job is then NULL).  rf_search_segment_end
+ * waits for the search (one synchronisation of `stream`), enqueues the exact
+ * recomputation of the images whose median left the bracket on `stream` and
+ * frees the job; its status is the search's.  The results are complete in
+ * `stream` order after rf_search_segment_end (as after rf_search_segment).
+ * Between the two calls every buffer stays in use by the search; every
+ * begin must be ended once.  Results are those of rf_search_segment, bit
+ * for bit.
+ */
+typedef struct rf_segment_job rf_segment_job;
+rf_status rf_search_segment_begin(const rf_plan *plan, const void *d_vis, rf_candidate *d_cand,
+                                  int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,
+                                  void *d_ws, size_t ws_bytes, void *stream,
+                                  rf_segment_job **job);
+rf_status rf_search_segment_end(rf_segment_job *job);
 
 /* Device time of the fused path's kernels, per kernel kind, measured with
  * HIP events on the stream each kernel is launched on

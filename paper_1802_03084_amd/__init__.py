@@ -329,17 +329,51 @@ class Plan:
         torch = _torch()
         self._check_vis(vis, self.nint)
         op = RF_OP_SEGMENT_STEPS if steps else RF_OP_SEGMENT
-        if ws is None:
-            ws = self.workspace(op)
-        cand = torch.empty((max(cap, 1), 8), dtype=torch.int32, device=self.device)
-        ncand = torch.zeros(1, dtype=torch.int32, device=self.device)
-        stats = torch.empty((self.n_images, 5), dtype=torch.int32, device=self.device) if with_stats else None
+        with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+            if ws is None:
+                ws = self.workspace(op)
+            cand = torch.empty((max(cap, 1), 8), dtype=torch.int32, device=self.device)
+            ncand = torch.empty(1, dtype=torch.int32, device=self.device)  # zeroed by the search
+            stats = (torch.empty((self.n_images, 5), dtype=torch.int32, device=self.device)
+                     if with_stats else None)
         fn = _lib.load().rf_search_segment_steps if steps else _lib.load().rf_search_segment
         _lib.check(fn(self._h, _ptr(vis), _ptr(cand), int(cap), _ptr(ncand), _ptr(stats), _ptr(ws),
                       ws.numel(), _stream(stream)), "rf_search_segment" + ("_steps" if steps else ""))
         if not collect:
             return cand, ncand, stats
+        if stream is not None:  # results are complete in that stream's order
+            stream.synchronize()
         return self._collect(cand, ncand, stats, cap)
+
+    def search_segment_begin(self, vis, cap=65536, with_stats=False, ws=None, stream=None):
+        """rf_search_segment_begin: enqueues the fused search and returns at
+        once; pass the result to search_segment_end for the candidates."""
+        torch = _torch()
+        self._check_vis(vis, self.nint)
+        # buffers belong to the search's stream; the search sets the count to
+        # zero itself (no fill on another stream that could race with it)
+        with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+            if ws is None:
+                ws = self.workspace(RF_OP_SEGMENT)
+            cand = torch.empty((max(cap, 1), 8), dtype=torch.int32, device=self.device)
+            ncand = torch.empty(1, dtype=torch.int32, device=self.device)
+            stats = (torch.empty((self.n_images, 5), dtype=torch.int32, device=self.device)
+                     if with_stats else None)
+        job = ctypes.c_void_p()
+        _lib.check(_lib.load().rf_search_segment_begin(self._h, _ptr(vis), _ptr(cand), int(cap), _ptr(ncand),
+                                                       _ptr(stats), _ptr(ws), ws.numel(), _stream(stream),
+                                                       ctypes.byref(job)), "rf_search_segment_begin")
+        return {"job": job, "keep": (vis, ws, cand, ncand, stats), "cap": int(cap),
+                "stream": stream if stream is not None else _torch().cuda.current_stream()}
+
+    def search_segment_end(self, pending):
+        """rf_search_segment_end: waits, runs the exact fallbacks (enqueued on
+        the search's stream); returns as search_segment once that stream is
+        done."""
+        _lib.check(_lib.load().rf_search_segment_end(pending["job"]), "rf_search_segment_end")
+        pending["stream"].synchronize()
+        _, _, cand, ncand, stats = pending["keep"]
+        return self._collect(cand, ncand, stats, pending["cap"])
 
     def periodic_workspace_bytes(self):
         n = _lib.c_size(0)

@@ -106,6 +106,9 @@ SIGNATURES = {
     "rf_image_static_max_bytes": (c_i32, [ctypes.POINTER(c_size)]),
     "rf_search": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_size, c_vp]),
     "rf_search_segment": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_size, c_vp]),
+    "rf_search_segment_begin": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_size, c_vp,
+                                        ctypes.POINTER(c_vp)]),
+    "rf_search_segment_end": (c_i32, [c_vp]),
     "rf_search_segment_steps": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_size, c_vp]),
     "rf_search_segment_profile": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_size, c_vp,
                                           ctypes.POINTER(KernelTimes)]),

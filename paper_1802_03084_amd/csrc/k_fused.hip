@@ -1420,6 +1420,60 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
   return RF_OK;
 }
 
+// A segment search split in two: begin enqueues everything but the exact
+// fallback and returns at once; end waits for the fallback list, recomputes
+// the listed images and frees the job (its lane streams live until then).
+struct rf_segment_job {
+  const rf_plan *p;
+  const void *vis;
+  rf_candidate *cand;
+  int cap;
+  int32_t *ncand;
+  rf_image_stats *stats;
+  char *ws;
+  int32_t *fb;
+  hipStream_t s;
+  Lanes lanes;
+};
+
+rf_status segment_begin(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
+                        int32_t *ncand, rf_image_stats *stats, void *ws_v, size_t ws_bytes,
+                        hipStream_t s, rf_segment_job **out) {
+  rf_segment_job *j = new rf_segment_job();
+  j->p = p;
+  j->vis = vis;
+  j->cand = cand;
+  j->cap = cap;
+  j->ncand = ncand;
+  j->stats = stats;
+  j->ws = static_cast<char *>(ws_v);
+  j->fb = (int32_t *)(j->ws + layout_of(p).fb);
+  j->s = s;
+  if (j->lanes.init() != hipSuccess) {
+    delete j;
+    return RF_EHIP;
+  }
+  Timer none;
+  none.streams.push_back(s);
+  const rf_status st = segment_enqueue(p, vis, cand, cap, ncand, stats, j->ws, ws_bytes, j->fb, s,
+                                       &j->lanes, false, &none);
+  if (st != RF_OK) {
+    delete j;  // drains the lane streams
+    return st;
+  }
+  *out = j;
+  return RF_OK;
+}
+
+rf_status segment_end(rf_segment_job *j) {
+  Timer none;
+  none.streams.push_back(j->s);
+  const rf_status st =
+      segment_finish(j->p, j->vis, j->cand, j->cap, j->ncand, j->stats, j->ws, j->fb, j->s, &none);
+  delete j;
+  return st;
+}
+
 // ------------------------------------------------------------------ batches
 // A batch searches several segments (plans of any shapes) bound once: the
 // segments run in order, sharing one workspace, each with its own fallback

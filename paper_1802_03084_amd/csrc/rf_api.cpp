@@ -644,6 +644,26 @@ rf_status rf_search_segment(const rf_plan *p, const void *d_vis, rf_candidate *d
                      (hipStream_t)stream, nullptr);
 }
 
+rf_status rf_search_segment_begin(const rf_plan *p, const void *d_vis, rf_candidate *d_cand,
+                                  int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,
+                                  void *d_ws, size_t ws_bytes, void *stream,
+                                  rf_segment_job **job) {
+  if (!job) return RF_EINVAL;
+  *job = nullptr;
+  if (!p) return RF_EINVAL;
+  if (cap < 0) return RF_ERANGE;
+  if (!d_vis || !d_ncand || (cap > 0 && !d_cand)) return RF_EINVAL;
+  if (ws_bytes < segment_ws_bytes(p)) return RF_EWORKSPACE;
+  if (!d_ws) return RF_EINVAL;
+  return segment_begin(p, d_vis, d_cand, cap, d_ncand, d_stats, d_ws, ws_bytes,
+                       (hipStream_t)stream, job);
+}
+
+rf_status rf_search_segment_end(rf_segment_job *job) {
+  if (!job) return RF_EINVAL;
+  return segment_end(job);
+}
+
 rf_status rf_search_segment_profile(const rf_plan *p, const void *d_vis, rf_candidate *d_cand,
                                     int32_t cap, int32_t *d_ncand, rf_image_stats *d_stats,
                                     void *d_ws, size_t ws_bytes, void *stream,

@@ -142,6 +142,10 @@ rf_status run_segment_steps(const rf_plan *p, const void *vis, rf_candidate *can
 rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
                       int32_t *ncand, rf_image_stats *stats, void *ws, size_t ws_bytes,
                       hipStream_t s, rf_kernel_times *kt);
+rf_status segment_begin(const rf_plan *p, const void *vis, rf_candidate *cand, int cap,
+                        int32_t *ncand, rf_image_stats *stats, void *ws, size_t ws_bytes,
+                        hipStream_t s, rf_segment_job **out);
+rf_status segment_end(rf_segment_job *j);
 size_t batch_ws_bytes(const rf_plan *const *plans, int nseg, size_t *main_bytes);
 rf_status batch_create(const rf_plan *const *plans, int nseg, const void *const *d_vis,
                        rf_candidate *const *d_cand, const int32_t *cap, int32_t *const *d_ncand,

@@ -138,6 +138,16 @@ def test_server_arguments_rejected_without_gpu():
     assert L.rf_server_destroy(None) == -1
 
 
+def test_segment_begin_end_arguments_rejected_without_gpu():
+    L = lib()
+    job = ctypes.c_void_p(123)
+    assert L.rf_search_segment_begin(None, None, None, 0, None, None, None, 0, None,
+                                     ctypes.byref(job)) == -1
+    assert job.value is None  # *job cleared on error
+    assert L.rf_search_segment_begin(None, None, None, 0, None, None, None, 0, None, None) == -1
+    assert L.rf_search_segment_end(None) == -1
+
+
 def test_tuning_and_batch_arguments_rejected_without_gpu():
     L = lib()
     out = ctypes.c_void_p(123)

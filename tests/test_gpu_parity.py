@@ -331,3 +331,26 @@ def test_fused_bright_source_exact_fallback_2048(torch):
     assert abs(s["peak"] - peak) <= TOL32 * amax
     assert abs(s["sigma"] - sigma) <= 1.4826 * TOL32 * amax
     assert s["snr"] > 50
+
+
+def test_segment_begin_end_equals_search(torch):
+    """rf_search_segment_begin / _end: two searches in flight at once on two
+    streams (a bright-source segment whose image takes the exact fallback,
+    and a plain one), each equal to rf_search_segment bit for bit."""
+    pa = rfgen.tiny()
+    pa.pulses = [rfgen.Pulse(dm_idx=1, width_idx=0, t0=3, x=140, y=120, snr=400.0)]
+    pb = rfgen.smallcase(seed=23)
+    say("segment begin/end")
+    out = []
+    for p in (pa, pb):
+        g = gpu_plan(p)
+        dv = upload(p.make_vis())
+        out.append((g, dv, g.search_segment(dv, cap=4096, with_stats=True)))
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    jobs = [g.search_segment_begin(dv, cap=4096, with_stats=True, stream=st)
+            for (g, dv, _), st in zip(out, (s1, s2))]
+    for (g, dv, (rows0, n0, st0)), job in zip(out, jobs):
+        rows, n, st = g.search_segment_end(job)
+        assert n == n0 and np.array_equal(rows, rows0)
+        assert np.array_equal(st.view(np.int32), st0.view(np.int32))
