@@ -306,15 +306,17 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
     float2 *__restrict__ M, float *__restrict__ epart) {
   constexpr int PBW = RowPairCfg<N>::PBW, F = RowPairCfg<N>::F, NT = RowPairCfg<N>::NT;
   constexpr int S = RowPairCfg<N>::STRIDE, PS = RowFft<N>::PS;
-  __shared__ float2 buf[F * S];
+  __shared__ __align__(16) float2 buf[F * S];
   __shared__ float s_e[2 * PBW];
+  static_assert((F * S) % 2 == 0, "the LDS buffer is cleared 16 bytes at a time");
   const int rp = blockIdx.x % n_rp;
   const int pb0 = (blockIdx.x / n_rp) * PBW;  // first pair of this block, batch-local
   const int tid = threadIdx.x;
   const int r = rp_row[rp];
   const int rm = (N - r) & (N - 1);
   const bool two = rm != r;
-  for (int i = tid; i < F * S; i += NT) buf[i] = make_float2(0.f, 0.f);
+  for (int i = tid; i < F * S / 2; i += NT)
+    reinterpret_cast<float4 *>(buf)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   if (tid < 2 * PBW) s_e[tid] = 0.f;
   __syncthreads();
   const int z0 = zs_off[rp], nz = zs_off[rp + 1] - z0;
