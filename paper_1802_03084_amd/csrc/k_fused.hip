@@ -1199,9 +1199,11 @@ rf_status drs_timed(const rf_plan *p, const int32_t *d_delay_row, const void *vi
       ++n;
     }
     ws.nw = n;
-    // 32 integrations per thread (or the widths' least common multiple):
-    // measured 1211 us per survey DM trial against 1230 us at 64
-    const int tchunk = L * std::max(1, 32 / L);
+    // 16 integrations per thread (or the widths' least common multiple):
+    // measured 1170 us per survey DM trial against 1177 us at 8, 1192 at 24,
+    // 1212 at 32 and 1229 at 64 (with 256 threads and 8 loads in flight per
+    // thread; 128 or 512 threads, 4, 12 or 16 loads in flight were slower)
+    const int tchunk = L * std::max(1, 16 / L);
     dim3 grid((nbc + kDrsThreads - 1) / kDrsThreads, (p->nint + tchunk - 1) / tchunk);
     const dim3 blk(kDrsThreads);
     if (p->vis_dtype == RF_CF32) {
