@@ -53,7 +53,7 @@ TableLayout table_layout(const rf_plan_desc *d) {
   L.zs_u = take(sizeof(int32_t) * 2 * bc);
   L.zs_ck = take(sizeof(int32_t) * 2 * bc);
   L.zs_cmk = take(sizeof(int32_t) * 2 * bc);
-  L.cblk = take(sizeof(int32_t) * (bc + 2));
+  L.cblk = take(sizeof(int4) * (bc + 1));
   L.total = o;
   return L;
 }
@@ -176,7 +176,7 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
   p->d_zs_u = (int32_t *)(base + L.zs_u);
   p->d_zs_ck = (int32_t *)(base + L.zs_ck);
   p->d_zs_cmk = (int32_t *)(base + L.zs_cmk);
-  p->d_cblk = (int32_t *)(base + L.cblk);
+  p->d_cblk = (int4 *)(base + L.cblk);
   p->d_freq = d_freq;
   p->d_uvw = d_uvw;
 
@@ -308,8 +308,13 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
     RF_HIP_TRY(hipMemcpyAsync(p->d_rp_sa, rp_sa.data(), rb, hipMemcpyHostToDevice, s));
     RF_HIP_TRY(hipMemcpyAsync(p->d_rp_sb, rp_sb.data(), rb, hipMemcpyHostToDevice, s));
   }
-  RF_HIP_TRY(hipMemcpyAsync(p->d_cblk, cblk.data(), sizeof(int32_t) * cblk.size(),
-                            hipMemcpyHostToDevice, s));
+  // per block: its cells and its run of contributors, in one 16-byte entry
+  std::vector<int4> cblk4(p->n_cblk);
+  for (int32_t b = 0; b < p->n_cblk; ++b)
+    cblk4[b] = make_int4(cblk[b], cblk[b + 1], off[cblk[b]], off[cblk[b + 1]]);
+  if (p->n_cblk > 0)
+    RF_HIP_TRY(hipMemcpyAsync(p->d_cblk, cblk4.data(), sizeof(int4) * cblk4.size(),
+                              hipMemcpyHostToDevice, s));
   if (p->n_zs > 0) {
     const size_t zb = sizeof(int32_t) * p->n_zs;
     RF_HIP_TRY(hipMemcpyAsync(p->d_zs_u, zs_u.data(), zb, hipMemcpyHostToDevice, s));

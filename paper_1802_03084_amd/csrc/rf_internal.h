@@ -49,10 +49,11 @@ struct rf_plan {
   // index (into d_ucell) at (v, u) and zs_cmk the one at (-v, -u), -1 where
   // the grid is empty.  Row -v's positions are the mirrors (-u).
   int32_t n_rp, n_zs;
-  // cell blocks for the staged gather: block b is cells cblk[b] .. cblk[b+1]-1,
-  // at most 1024 contributors (a single heavier cell forms its own block)
+  // cell blocks for the staged gather: block b is cells cblk[b].x ..
+  // cblk[b].y - 1, whose contributors are cblk[b].z .. cblk[b].w - 1 of
+  // d_contrib, at most 1024 (a single heavier cell forms its own block)
   int32_t n_cblk;
-  int32_t *d_cblk;          // [n_cblk + 1]
+  int4 *d_cblk;             // [n_cblk]
   double *d_freq;           // [nchan] channel centres, GHz
   double *d_uvw;            // [nbl][3] baseline vectors, metres
   int32_t *d_rp_row;        // [n_rp]
