@@ -646,7 +646,11 @@ __device__ __forceinline__ void sel_bin(const uint32_t *hist, uint32_t rank, uin
 }
 
 constexpr int kMaxCB = 512;       // column workgroups per image, at most
-constexpr int kLdsVals = 20480;   // bracket values staged in LDS (80 KB)
+// bracket values staged in LDS: about 0.86% of the pixels per percent of
+// bracket half-width (6,300 at 1024^2, 14,400 at 2048^2), with room to spare;
+// more send the image to the exact fallback
+template <int N>
+constexpr int lds_vals_of() { return N >= 2048 ? 20480 : (N >= 1024 ? 10240 : 8192); }
 
 // Per image: combines the column workgroups' records (peak, count below the
 // bracket, per-wave bracket counts), stages every kept bracket magnitude in
@@ -677,9 +681,11 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
   __shared__ float s_v;
   __shared__ int32_t s_i;
   __shared__ uint32_t s_lo, s_n, s_of;
-  __shared__ uint32_t r_off[kMaxCB * NWC];  // LDS offset of (workgroup, wave) values
-  __shared__ uint32_t r_cnt[kMaxCB * NWC];  // and their number
-  __shared__ float vals[kLdsVals];
+  constexpr int CBN = N / ColCfg<N>::COLS;        // column workgroups per image
+  constexpr int NV = lds_vals_of<N>();
+  __shared__ uint32_t r_off[CBN * NWC];  // LDS offset of (workgroup, wave) values
+  __shared__ uint32_t r_cnt[CBN * NWC];  // and their number
+  __shared__ float vals[NV];
   __shared__ float binv[kBinCap];
   __shared__ uint32_t s_nc;
   __shared__ float s_med;
@@ -690,8 +696,8 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const ColPart *pp = part + (size_t)il * cbn;
   {  // combine the column workgroups' records; workgroup r's values go to
-     // LDS from r_off[r * NWC] (kMaxCB / kSelThreads consecutive records per thread)
-    constexpr int RPT = kMaxCB > kSelThreads ? kMaxCB / kSelThreads : 1;
+     // LDS from r_off[r * NWC] (CBN / kSelThreads consecutive records per thread)
+    constexpr int RPT = CBN > kSelThreads ? CBN / kSelThreads : 1;
     float v = -__builtin_inff();
     int32_t i = 0x7fffffff;
     uint32_t lo = 0, nn = 0, of = 0, cnt[RPT][NWC];
@@ -776,7 +782,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
   const int32_t pidx_ = s_i;
   const uint32_t rank = (uint32_t)(((size_t)npix * npix - 1) / 2);
   const uint32_t n = s_n;
-  const bool ovf = s_of != 0 || n > (uint32_t)kLdsVals;
+  const bool ovf = s_of != 0 || n > (uint32_t)NV;
   float med;
   if (peak == 0.f && s_lo == 0 && n == 0) {
     med = 0.f;  // identically zero image (every pixel equals the zero peak)
