@@ -108,11 +108,13 @@ __device__ __forceinline__ void load_pols(const __half2 *vis, size_t e, int P, f
 
 // Dedisperse + boxcar-resample to every width in `ws` + Stokes I, one thread
 // per (baseline, channel) walking a chunk of integrations that starts at a
-// multiple of every width.  Sums run per polarisation in increasing time and
-// are scaled by 1/w (the float reciprocal, exact for powers of two) before
-// the polarisations are averaged, exactly as rf_resample followed by
-// rf_grid's Stokes I.  Output per width:
-// VI_w[k][bc], coalesced along bc.
+// multiple of every width and holds an even number of each width's images.
+// Sums run per polarisation in increasing time and are scaled by 1/w (the
+// float reciprocal, exact for powers of two) before the polarisations are
+// averaged, exactly as rf_resample followed by rf_grid's Stokes I.  Output
+// per width, by image pair (the pairs of the paired transform):
+// VI_w[k / 2][bc][k % 2], one 16-byte store per pair, coalesced along bc; the
+// odd last image of a width is paired with zeros.
 template <typename Ein, int P>
 __global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis,
                                                      const int32_t *__restrict__ delay, int nint,
@@ -122,17 +124,25 @@ __global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis
   const int d = delay[bc % nchan];
   const int t0 = blockIdx.y * tchunk;
   const int t1 = min(nint, t0 + tchunk);
-  float2 a0[kMaxW], a1[kMaxW];
+  float2 a0[kMaxW], a1[kMaxW], held[kMaxW];  // held: first image of the open pair
   int cnt[kMaxW], kout[kMaxW];
   float inv[kMaxW];  // 1/w: exact for powers of two, so the product is the quotient
 #pragma unroll
   for (int j = 0; j < kMaxW; ++j) {
     a0[j] = make_float2(0.f, 0.f);
     a1[j] = a0[j];
+    held[j] = a0[j];
     cnt[j] = 0;
     inv[j] = j < ws.nw ? 1.0f / (float)ws.w[j] : 0.f;
-    kout[j] = j < ws.nw ? t0 / ws.w[j] : 0;  // t0 is a multiple of every width
+    kout[j] = j < ws.nw ? t0 / ws.w[j] : 0;  // even: t0 is an even multiple of every width
   }
+  // each sample is read once, batches later: stream it past the caches
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  auto put = [&](int j, float2 x, float2 y) {
+    const f4v v = {x.x, x.y, y.x, y.y};
+    __builtin_nontemporal_store(
+        v, reinterpret_cast<f4v *>(&ws.out[j][((size_t)(kout[j] >> 1) * nbc + bc) * 2]));
+  };
   constexpr int U = 8;  // integrations loaded ahead: U loads in flight per thread
   for (int tb = t0; tb < t1; tb += U) {
     float2 w0[U], w1[U];
@@ -169,11 +179,10 @@ __global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis
             } else {
               vi = make_float2(a0[j].x * iw, a0[j].y * iw);
             }
-            // each sample is read once, batches later: stream it past the caches
-            typedef float f2v __attribute__((ext_vector_type(2)));
-            const f2v x2 = {vi.x, vi.y};
-            __builtin_nontemporal_store(x2,
-                                        reinterpret_cast<f2v *>(&ws.out[j][(size_t)kout[j] * nbc + bc]));
+            if (kout[j] & 1)  // uniform: every thread of the workgroup shares t0
+              put(j, held[j], vi);
+            else
+              held[j] = vi;
             ++kout[j];
             a0[j] = make_float2(0.f, 0.f);
             a1[j] = a0[j];
@@ -183,103 +192,101 @@ __global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis
       }
     }
   }
+  // a chunk cut short by the end of the segment can close on the first image
+  // of a pair: the width's last image, paired with zeros
+#pragma unroll
+  for (int j = 0; j < kMaxW; ++j)
+    if (j < ws.nw && (kout[j] & 1)) put(j, held[j], make_float2(0.f, 0.f));
 }
 
 // ------------------------------------------------------------------ rows
 // Gridding as a gather: CV[i][c] = sum of the Stokes I samples of uv cell c
 // for image i of a batch, in the plan's contributor order (the same sums as
 // rf_grid).  A workgroup takes a block of whole cells (at most 1024
-// contributors) for a group of kCellImgs images: it stages the block's
-// samples in LDS with all loads in flight, then one thread per cell sums them
-// in contributor order.  All blocks of one image group run on one XCD (blocks
-// are dealt to the eight XCDs round robin), so the group's samples stay in
-// that XCD's L2; a batch of fewer than eight groups spreads each group's
-// blocks over 8 / groups XCDs instead.
+// contributors) for one image pair: it stages the block's samples in LDS
+// with all loads in flight (one 16-byte load per contributor: the two images
+// of a pair sit side by side), then one thread per cell sums them in
+// contributor order.  Output by pair: CV[p][c] = (image 2p, image 2p + 1).
+// All blocks of one pair run on one XCD (blocks are dealt to the eight XCDs
+// round robin), so the pair's samples stay in that XCD's L2; a batch of fewer
+// than eight pairs spreads each pair's blocks over 8 / pairs XCDs instead.
 constexpr int kCellThreads = 256;
-// images per workgroup: the block's contributor indices are loaded once for
-// them (2 rather than 4: twice the workgroups, whose gathers keep more loads
-// in flight across the device; measured 16.2 -> 14.6 us per survey batch)
-constexpr int kCellImgs = 2;
 constexpr int kCellBlock = 1024;   // contributors staged per workgroup
 
 __global__ __launch_bounds__(kCellThreads) void k_cellsum(
-    const float2 *__restrict__ vi, int nbc, int k0, int nimg, int n_cells, int n_cblk,
+    const float4 *__restrict__ vi, int nbc, int p0, int npair, int n_cells, int n_cblk,
     const int4 *__restrict__ cblk, const int32_t *__restrict__ coff,
-    const int32_t *__restrict__ contrib, float2 *__restrict__ cv, int rep) {
-  __shared__ float2 val[kCellBlock * kCellImgs];
+    const int32_t *__restrict__ contrib, float4 *__restrict__ cv, int rep) {
+  __shared__ float4 val[kCellBlock];
   const int b = blockIdx.x, xcd = b & 7, local = b >> 3;
-  int g, blk;  // group of kCellImgs images within the batch, cell block
-  if (rep == 1) {  // at least eight groups: every block of a group on one XCD
+  int g, blk;  // image pair within the batch, cell block
+  if (rep == 1) {  // at least eight pairs: every block of a pair on one XCD
     g = (local / n_cblk) * 8 + xcd;
     blk = local % n_cblk;
-  } else {  // fewer groups: `rep` XCDs share a group's blocks
+  } else {  // fewer pairs: `rep` XCDs share a pair's blocks
     g = xcd / rep;
     blk = local * rep + xcd % rep;
     if (blk >= n_cblk) return;
   }
-  const int i0 = g * kCellImgs;
-  if (i0 >= nimg) return;
+  if (g >= npair) return;
   const int tid = threadIdx.x;
-  const float2 *v = vi + (size_t)(k0 + i0) * nbc;
+  const float4 *v = vi + (size_t)(p0 + g) * nbc;
   // the block's cells and contributor run in one load: one level of
   // dependent loads fewer before the gather
   const int4 bk = cblk[blk];
   const int c0 = bk.x, c1 = bk.y, q0 = bk.z, q1 = bk.w, nq = q1 - q0;
+  float4 *out = cv + (size_t)g * n_cells;
+  auto add = [](float4 &acc, const float4 y) {
+    acc.x += y.x;
+    acc.y += y.y;
+    acc.z += y.z;
+    acc.w += y.w;
+  };
   if (nq <= kCellBlock) {
-    // stage the block's samples: every index load, then every value load, in flight together
+    // stage the block's samples: every index load, then every value load, in
+    // flight together.  Every slot of the stage is written (slots past the
+    // block hold a copy of its last sample and are never summed), so no
+    // branch separates a load from its use and none waits for another.
     constexpr int T = kCellBlock / kCellThreads;
     int bq[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) bq[t] = contrib[min(q0 + tid + t * kCellThreads, q1 - 1)];
-    float2 x[T][kCellImgs];
+    // the contributor range of this thread's first cell, fetched alongside
+    const int cf = min(c0 + tid, c1 - 1);
+    int f0 = coff[cf], f1 = coff[cf + 1];
+    float4 x[T];
 #pragma unroll
-    for (int t = 0; t < T; ++t)
+    for (int t = 0; t < T; ++t) x[t] = v[bq[t]];
 #pragma unroll
-      for (int m = 0; m < kCellImgs; ++m)
-        x[t][m] = v[(size_t)min(m, nimg - 1 - i0) * nbc + bq[t]];
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int q = tid + t * kCellThreads;
-      if (q < nq)
-#pragma unroll
-        for (int m = 0; m < kCellImgs; ++m) val[q * kCellImgs + m] = x[t][m];
-    }
+    for (int t = 0; t < T; ++t) val[tid + t * kCellThreads] = x[t];
+    asm volatile("" ::"v"(f0), "v"(f1));  // keeps the range load ahead of the barrier
     __syncthreads();
     for (int c = c0 + tid; c < c1; c += kCellThreads) {
-      float2 acc[kCellImgs];
-#pragma unroll
-      for (int m = 0; m < kCellImgs; ++m) acc[m] = make_float2(0.f, 0.f);
-      const int e = coff[c + 1] - q0;
-      for (int q = coff[c] - q0; q < e; ++q)
-#pragma unroll
-        for (int m = 0; m < kCellImgs; ++m) {
-          const float2 y = val[q * kCellImgs + m];
-          acc[m].x += y.x;
-          acc[m].y += y.y;
-        }
-#pragma unroll
-      for (int m = 0; m < kCellImgs; ++m)
-        if (i0 + m < nimg) cv[(size_t)(i0 + m) * n_cells + c] = acc[m];
+      if (c != c0 + tid) {
+        f0 = coff[c];
+        f1 = coff[c + 1];
+      }
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      const int e = f1 - q0;
+      int q = f0 - q0;
+      // four reads in flight, then the adds in contributor order
+      for (; q + 4 <= e; q += 4) {
+        const float4 y0 = val[q], y1 = val[q + 1], y2 = val[q + 2], y3 = val[q + 3];
+        add(acc, y0);
+        add(acc, y1);
+        add(acc, y2);
+        add(acc, y3);
+      }
+      for (; q < e; ++q) add(acc, val[q]);
+      out[c] = acc;
     }
   } else {
     // a cell with more contributors than a block: direct gather, same order
     for (int c = c0 + tid; c < c1; c += kCellThreads) {
-      float2 acc[kCellImgs];
-#pragma unroll
-      for (int m = 0; m < kCellImgs; ++m) acc[m] = make_float2(0.f, 0.f);
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
       const int e = coff[c + 1];
-      for (int q = coff[c]; q < e; ++q) {
-        const int bcq = contrib[q];
-#pragma unroll
-        for (int m = 0; m < kCellImgs; ++m) {
-          const float2 y = v[(size_t)min(m, nimg - 1 - i0) * nbc + bcq];
-          acc[m].x += y.x;
-          acc[m].y += y.y;
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < kCellImgs; ++m)
-        if (i0 + m < nimg) cv[(size_t)(i0 + m) * n_cells + c] = acc[m];
+      for (int q = coff[c]; q < e; ++q) add(acc, v[contrib[q]]);
+      out[c] = acc;
     }
   }
 }
@@ -303,7 +310,7 @@ struct RowPairCfg {
 
 template <int N>
 __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
-    const float2 *__restrict__ cv, int n_cells, int nk, int p0, int pbn,
+    const float4 *__restrict__ cv, int n_cells, int nk, int p0, int pbn,
     const int32_t *__restrict__ rp_row, const int32_t *__restrict__ rp_sa,
     const int32_t *__restrict__ rp_sb, int n_rp, int n_rows, const int32_t *__restrict__ zs_off,
     const int32_t *__restrict__ zs_u, const int32_t *__restrict__ zs_ck,
@@ -335,14 +342,14 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
     if (pl >= pbn) continue;
     const bool hasb = 2 * (p0 + pl) + 1 < nk;
     const int u = zs_u[z], ck = zs_ck[z], cmk = zs_cmk[z];
-    // cell sums of images a and b; absent cells (and an absent image b) read
-    // zero through the buffer range check
-    const auto rca = buf_rsrc(cv + (size_t)(2 * pl) * n_cells, (uint32_t)n_cells * 8u);
-    const auto rcb = buf_rsrc(cv + (size_t)(2 * pl + 1) * n_cells, hasb ? (uint32_t)n_cells * 8u : 0u);
-    const uint32_t ok = ck >= 0 ? (uint32_t)ck * 8u : kNoLoad;
-    const uint32_t om = cmk >= 0 ? (uint32_t)cmk * 8u : kNoLoad;
-    const float2 ga = buf_load_f2(rca, ok), gam = buf_load_f2(rca, om);
-    const float2 gb = buf_load_f2(rcb, ok), gbm = buf_load_f2(rcb, om);
+    // cell sums of images a and b side by side; absent cells read zero
+    // through the buffer range check, an absent image b is zero
+    const auto rc = buf_rsrc(cv + (size_t)pl * n_cells, (uint32_t)n_cells * 16u);
+    const float4 c4 = buf_load_f4(rc, ck >= 0 ? (uint32_t)ck * 16u : kNoLoad);
+    const float4 m4 = buf_load_f4(rc, cmk >= 0 ? (uint32_t)cmk * 16u : kNoLoad);
+    const float2 ga = make_float2(c4.x, c4.y), gam = make_float2(m4.x, m4.y);
+    const float2 gb = hasb ? make_float2(c4.z, c4.w) : make_float2(0.f, 0.f);
+    const float2 gbm = hasb ? make_float2(m4.z, m4.w) : make_float2(0.f, 0.f);
     const float sg = ((r + u) & 1) ? -hw : hw;  // (-1)^(u+v) / (2W)
     buf[pp * S + pidx<PS>(u)] = zval(ga, gam, gb, gbm, sg);
     if (two) buf[(PBW + pp) * S + pidx<PS>((N - u) & (N - 1))] = zval(gam, ga, gbm, gb, sg);
@@ -968,9 +975,9 @@ Layout layout_of(const rf_plan *p) {
   const size_t nbc = (size_t)p->nbl * p->nchan;
   const size_t np2 = (size_t)p->npix * p->npix;
   size_t o = 0, vi_elems = 0;
-  for (int j = 0; j < p->nwidth; ++j) {
+  for (int j = 0; j < p->nwidth; ++j) {  // by image pair: [k / 2][bc][k % 2]
     L.vi_off.push_back(vi_elems);
-    vi_elems += (size_t)(p->nint / p->width[j]) * nbc;
+    vi_elems += (size_t)((p->nint / p->width[j] + 1) / 2) * 2 * nbc;
   }
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -1138,20 +1145,20 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
                   const LaneBufs &B, int32_t *fb, rf_image_stats *stats, rf_candidate *cand,
                   int cap, int32_t *ncand, hipStream_t s, Timer *tm) {
   float2 *M = (float2 *)(ws + B.m);
-  float2 *cv = (float2 *)(ws + B.cv);
+  float4 *cv = (float4 *)(ws + B.cv);
   float *epart = (float *)(ws + B.epart);
   ColPart *part = (ColPart *)(ws + B.part);
   float *list = (float *)(ws + B.list);
   const int npb = (pbn + sh.pbw - 1) / sh.pbw;
   const int nimg_b = std::min(2 * pbn, nimg_w - 2 * p0);  // images in this batch
-  // image groups; with fewer than eight, several XCDs share each group's cell
+  // image pairs; with fewer than eight, several XCDs share each pair's cell
   // blocks so that no XCD idles
-  const int ngrp = (nimg_b + kCellImgs - 1) / kCellImgs;
-  const int rep = ngrp >= 8 ? 1 : 8 / ngrp;
-  const int per_xcd = rep == 1 ? (ngrp + 7) / 8 * p->n_cblk : (p->n_cblk + rep - 1) / rep;
-  RF_HIP_TRY(tm->launch(RF_K_GRID, k_cellsum, dim3(8 * per_xcd), dim3(kCellThreads), s, vi,
-                        p->nbl * p->nchan, 2 * p0, nimg_b, p->n_cells, p->n_cblk, p->d_cblk,
-                        p->d_ucell_off, p->d_contrib, cv, rep));
+  const int npair = (nimg_b + 1) / 2;
+  const int rep = npair >= 8 ? 1 : 8 / npair;
+  const int per_xcd = rep == 1 ? (npair + 7) / 8 * p->n_cblk : (p->n_cblk + rep - 1) / rep;
+  RF_HIP_TRY(tm->launch(RF_K_GRID, k_cellsum, dim3(8 * per_xcd), dim3(kCellThreads), s,
+                        (const float4 *)vi, p->nbl * p->nchan, p0, npair, p->n_cells,
+                        p->n_cblk, p->d_cblk, p->d_ucell_off, p->d_contrib, cv, rep));
   RF_HIP_TRY(tm->launch(RF_K_ROWS, k_rows_pairs<N>, dim3(npb * p->n_rp), dim3(RowPairCfg<N>::NT),
                         s, cv, p->n_cells, nimg_w, p0, pbn, p->d_rp_row, p->d_rp_sa, p->d_rp_sb,
                         p->n_rp, p->n_rows, p->d_zs_off, p->d_zs_u, p->d_zs_ck, p->d_zs_cmk,
@@ -1210,11 +1217,12 @@ rf_status drs_timed(const rf_plan *p, const int32_t *d_delay_row, const void *vi
       ++n;
     }
     ws.nw = n;
-    // 16 integrations per thread (or the widths' least common multiple):
-    // measured 1170 us per survey DM trial against 1177 us at 8, 1192 at 24,
-    // 1212 at 32 and 1229 at 64 (with 256 threads and 8 loads in flight per
-    // thread; 128 or 512 threads, 4, 12 or 16 loads in flight were slower)
-    const int tchunk = L * std::max(1, 16 / L);
+    // 16 integrations per thread (or the multiple of the widths' least common
+    // multiple that holds an even number of images of every width): measured
+    // 1170 us per survey DM trial against 1177 us at 8, 1192 at 24, 1212 at
+    // 32 and 1229 at 64 (with 256 threads and 8 loads in flight per thread;
+    // 128 or 512 threads, 4, 12 or 16 loads in flight were slower)
+    const int tchunk = L * std::max(2, (16 / L + 1) & ~1);
     dim3 grid((nbc + kDrsThreads - 1) / kDrsThreads, (p->nint + tchunk - 1) / tchunk);
     const dim3 blk(kDrsThreads);
     if (p->vis_dtype == RF_CF32) {
@@ -1237,12 +1245,6 @@ rf_status drs_timed(const rf_plan *p, const int32_t *d_delay_row, const void *vi
   return RF_OK;
 }
 }  // namespace
-
-rf_status launch_drs(const rf_plan *p, const int32_t *d_delay_row, const void *vis,
-                     const int *widths, int nw, float2 *const *vi_out, hipStream_t s) {
-  Timer none;
-  return drs_timed(p, d_delay_row, vis, widths, nw, vi_out, s, &none);
-}
 
 size_t segment_ws_bytes(const rf_plan *p) {
   if (p->W == 0 || p->n_rows == 0) return std::max(layout_of(p).total, steps_ws_bytes(p));
