@@ -385,6 +385,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, uint32
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
                                            0x00020000);
 }
+// The same for a pointer and size that are uniform across the wave, read
+// from its first lane so that the resource stays in scalar registers (a
+// resource the compiler cannot prove uniform is used in a loop over the
+// lanes' distinct values)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc_u(const void *p, uint32_t bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return buf_rsrc(reinterpret_cast<const void *>(((uint64_t)hi << 32) | lo),
+                  __builtin_amdgcn_readfirstlane(bytes));
+}
 __device__ __forceinline__ float2 buf_load_f2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   typedef unsigned int u2 __attribute__((ext_vector_type(2)));
   const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);

@@ -332,6 +332,10 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
   if (tid < 2 * PBW) s_e[tid] = 0.f;
   __syncthreads();
   const int z0 = zs_off[rp], nz = zs_off[rp + 1] - z0;
+  // cell sums of this workgroup's pairs, one resource for all of them (a
+  // per-lane resource would need a loop over its distinct values)
+  const float4 *cvw = cv + (size_t)pb0 * n_cells;
+  const uint32_t cvw_bytes = (uint32_t)(max(0, min(PBW, pbn - pb0)) * n_cells) * 16u;
   const float ew = two ? 0.5f : 0.25f;  // |H|^2 = |.|^2/4, counted twice for a row pair
   float e_acc[2 * PBW];                 // this thread's share of each image's energy
 #pragma unroll
@@ -344,9 +348,10 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
     const int u = zs_u[z], ck = zs_ck[z], cmk = zs_cmk[z];
     // cell sums of images a and b side by side; absent cells read zero
     // through the buffer range check, an absent image b is zero
-    const auto rc = buf_rsrc(cv + (size_t)pl * n_cells, (uint32_t)n_cells * 16u);
-    const float4 c4 = buf_load_f4(rc, ck >= 0 ? (uint32_t)ck * 16u : kNoLoad);
-    const float4 m4 = buf_load_f4(rc, cmk >= 0 ? (uint32_t)cmk * 16u : kNoLoad);
+    const auto rc = buf_rsrc_u(cvw, cvw_bytes);
+    const uint32_t pc = (uint32_t)(pp * n_cells);
+    const float4 c4 = buf_load_f4(rc, ck >= 0 ? (pc + (uint32_t)ck) * 16u : kNoLoad);
+    const float4 m4 = buf_load_f4(rc, cmk >= 0 ? (pc + (uint32_t)cmk) * 16u : kNoLoad);
     const float2 ga = make_float2(c4.x, c4.y), gam = make_float2(m4.x, m4.y);
     const float2 gb = hasb ? make_float2(c4.z, c4.w) : make_float2(0.f, 0.f);
     const float2 gbm = hasb ? make_float2(m4.z, m4.w) : make_float2(0.f, 0.f);
