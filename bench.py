@@ -604,11 +604,6 @@ def main():
                  "timing": "HIP start/stop events attached to each dispatch (hipExtLaunchKernel) "
                            "on the launch's stream, one search with the launches in order on one "
                            "stream (the kernel alone on the device)"})
-    if f_launch:
-        # the packed fp32 forms are not used (they are switched off in the
-        # build): one fp32 FMA per lane per cycle is half the published peak
-        roof["unpacked_fp32_peak_tflops"] = round(FP32_PEAK_TFLOPS / 2, 2)
-        roof["frac_of_unpacked"] = round(tfs / (FP32_PEAK_TFLOPS / 2), 4)
     if N == 1024 and traffic_per_dispatch(dom) is not None:
         roof["traffic"] = round(traffic_per_dispatch(dom))
         roof["traffic_unit"] = ("B per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE): for the "

@@ -204,11 +204,21 @@ __device__ __forceinline__ void fft_first_dft(FirstRegs<Sh, F, NT> &x) {
   for (int q = 0; q < X::Q; ++q) dft<X::R>(x.v[q]);
 }
 
+// Powers t[r] = b^r, r < R (t[0] = 1), each the product of two lower powers
+// (r = floor(r/2) + ceil(r/2)): at most log2 R products deep, so every power
+// stays within a few ulp of exp(+2 pi i r m / N) when b is a table value.
+template <int R>
+__device__ __forceinline__ void twiddle_powers(float2 b, float2 (&t)[R]) {
+  t[0] = make_float2(1.f, 0.f);
+  if constexpr (R > 1) t[1] = b;
+#pragma unroll
+  for (int r = 2; r < R; ++r) t[r] = cmul(t[r / 2], t[r - r / 2]);
+}
+
 // LDS write of the first pass; the caller synchronises before it (if buf is
 // still being read) and after.  With PRE, each output is first multiplied by
-// the twiddle that the second pass would apply to it when gathering (same
-// operands, same operation: bit-identical), and the second pass must then
-// run with its twiddles off.
+// the twiddle that the second pass would apply to it when gathering, and the
+// second pass must then run with its twiddles off.
 template <class Sh, int F, int NT, int S, bool JF, bool PRE = false>
 __device__ __forceinline__ void fft_first_store(float2 *buf, const float2 *__restrict__ tw, int tid,
                                                 FirstRegs<Sh, F, NT> &x) {
@@ -221,45 +231,51 @@ __device__ __forceinline__ void fft_first_store(float2 *buf, const float2 *__res
     if ((X::TOT % NT) == 0 || idx < X::TOT) {
       int f, j;
       fj_of<F, X::NB, JF>(idx, f, j);
+      // output r is element r1 = p / NB1 of second-pass butterfly p % NB1
+      // (p = j R0 + r), whose twiddle exponent is ((p % NB1) mod NS1) r1 TS1:
+      // since NB1 = R0 R2, r1 = j / R2 for every r and (p % NB1) mod NS1 = r,
+      // so the R0 twiddles are the powers of tw[(j / R2) TS1]
+      float2 t[X::R];
+      if constexpr (PRE) twiddle_powers<X::R>(tw[(j / Sh::R2) * TS1], t);
 #pragma unroll
       for (int r = 0; r < X::R; ++r) {
-        const int p = j * X::R + r;  // the second pass reads it as element p / NB1 of butterfly p % NB1
-        if constexpr (PRE) {
-          const int r1 = p / NB1, jm = (p % NB1) % NS1;
-          x.v[q][r] = cmul(x.v[q][r], tw[jm * r1 * TS1]);
-        }
+        const int p = j * X::R + r;
+        if constexpr (PRE) x.v[q][r] = cmul(x.v[q][r], t[r]);
         buf[f * S + pidx<PS>(p)] = x.v[q][r];
       }
     }
   }
 }
 
+// First pass with the second pass's twiddles applied at its store (PRE).
 template <class Sh, int F, int NT, int S, bool JF, class Load>
-__device__ __forceinline__ void fft_first(float2 *buf, int tid, Load load) {
+__device__ __forceinline__ void fft_first(float2 *buf, const float2 *__restrict__ tw, int tid,
+                                          Load load) {
   FirstRegs<Sh, F, NT> x;
   fft_first_load<Sh, F, NT, JF>(tid, load, x);
   __builtin_amdgcn_sched_barrier(0);  // every load issued before the transform starts
   fft_first_dft<Sh, F, NT>(x);
   __syncthreads();  // inputs may have come from buf
-  fft_first_store<Sh, F, NT, S, JF>(buf, nullptr, tid, x);
+  fft_first_store<Sh, F, NT, S, JF, true>(buf, tw, tid, x);
   __syncthreads();
 }
 
 // Loads butterfly (f, j) of a radix-R pass from LDS and applies the twiddles
-// w^(r (j mod NS)), w = exp(+2 pi i / (NS R)), from the global table
-// tw[m] = exp(+2 pi i m / N).  Every element is multiplied, r = 0 included
-// (by tw[0] = 1, exact up to the sign of a zero), so that no load sits
-// behind a branch.
+// w^(r (j mod NS)), w = exp(+2 pi i / (NS R)): the powers of the one table
+// value tw[(j mod NS) N / (NS R)] (tw[m] = exp(+2 pi i m / N)).  Every
+// element is multiplied, r = 0 included (by 1, exact up to the sign of a
+// zero).
 template <int N, int R, int NS, int S, int PS, bool TW = true>
 __device__ __forceinline__ void fft_gather(const float2 *buf, const float2 *__restrict__ tw, int f,
                                            int j, float2 (&v)[R]) {
   constexpr int NB = N / R;
+  float2 t[R];
+  if constexpr (TW) twiddle_powers<R>(tw[(j % NS) * (N / (NS * R))], t);
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = buf[f * S + pidx<PS>(j + r * NB)];
   if constexpr (TW) {
-    const int jm = j % NS;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = cmul(v[r], tw[jm * r * (N / (NS * R))]);
+    for (int r = 0; r < R; ++r) v[r] = cmul(v[r], t[r]);
   }
 }
 
@@ -351,15 +367,17 @@ __device__ __forceinline__ void fft_rest_blocks(float2 *buf, const float2 *__res
 
 // Inverse (exp(+i)) unnormalised FFT of F sequences of length N: inputs from
 // load(f, i), outputs to store(f, k, value), LDS buf of F * S elements
-// (S >= Sh::PADDED) for the exchanges between passes.
+// (S >= Sh::PADDED) for the exchanges between passes.  The second pass's
+// twiddles are applied by the first pass's store, as in every transform here,
+// so that all of them form the same twiddle values in the same way.
 template <class Sh, int F, int NT, int S, bool JF, class Load, class Store>
 __device__ __forceinline__ void fft_inverse(float2 *buf, const float2 *__restrict__ tw, int tid,
                                             Load load, Store store) {
-  fft_first<Sh, F, NT, S, JF>(buf, tid, load);
+  fft_first<Sh, F, NT, S, JF>(buf, tw, tid, load);
   if constexpr (Sh::R2 == 1) {
-    fft_last<Sh, Sh::R1, Sh::R0, F, NT, S, JF, true>(buf, tw, tid, store);
+    fft_last<Sh, Sh::R1, Sh::R0, F, NT, S, JF, false>(buf, tw, tid, store);
   } else {
-    fft_mid<Sh, Sh::R1, Sh::R0, F, NT, S, JF>(buf, tw, tid);
+    fft_mid<Sh, Sh::R1, Sh::R0, F, NT, S, JF, false>(buf, tw, tid);
     fft_last<Sh, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF, true>(buf, tw, tid, store);
   }
 }
