@@ -171,11 +171,59 @@ __device__ __forceinline__ void fj_of(int idx, int &f, int &j) {
   }
 }
 
-// First pass (no twiddles): inputs from load(f, i), radix-R0 DFT, results to
-// LDS at the Stockham position j R0 + r.  The pass comes in three parts
-// (fft_first_load: the inputs into registers; fft_first_dft; fft_first_store:
-// the LDS write) so that a caller can do other work while the loads are in
-// flight.
+// Powers t[r] = b^r, r < R (t[0] = 1), each the product of two lower powers
+// (r = floor(r/2) + ceil(r/2)): at most log2 R products deep, so every power
+// stays within a few ulp of exp(+2 pi i r m / N) when b is a table value.
+template <int R>
+__device__ __forceinline__ void twiddle_powers(float2 b, float2 (&t)[R]) {
+  t[0] = make_float2(1.f, 0.f);
+  if constexpr (R > 1) t[1] = b;
+#pragma unroll
+  for (int r = 2; r < R; ++r) t[r] = cmul(t[r / 2], t[r - r / 2]);
+}
+
+// Twiddles.  A radix-R pass multiplies element r of butterfly j by
+// w^(r (j mod NS)), w = exp(+2 pi i / (NS R)): the powers of one table value
+// per butterfly, tw[(j mod NS) N / (NS R)] (tw[m] = exp(+2 pi i m / N)).  The
+// second pass's twiddles are applied by the first pass as it stores (its
+// output r is element p / NB1 of second-pass butterfly p mod NB1, p = j R0 +
+// r; as NB1 = R0 R2 that element is j / R2 for every r and the butterfly's
+// j mod R0 is r, so the first pass's R0 twiddles are the powers of
+// tw[(j / R2) N / (R0 R1)]); the last pass of a three-pass shape applies
+// its own.  A thread therefore needs one table value per butterfly it takes
+// in the first pass and in the last, loaded once, ahead of every barrier.
+template <class Sh, int F, int NT, bool JF>
+struct TwBases {
+  static constexpr int N = Sh::N;
+  static constexpr int NB0 = N / Sh::R0, TOT0 = F * NB0, Q0 = (TOT0 + NT - 1) / NT;
+  static constexpr bool THREE = Sh::R2 != 1;
+  static constexpr int NBL = N / Sh::R2, TOTL = F * NBL, QL = THREE ? (TOTL + NT - 1) / NT : 1;
+  float2 first[Q0];
+  float2 last[QL];
+  __device__ __forceinline__ void load(const float2 *__restrict__ tw, int tid) {
+#pragma unroll
+    for (int q = 0; q < Q0; ++q) {  // threads past the butterflies load a value they never use
+      int f, j;
+      fj_of<F, NB0, JF>(min(tid + q * NT, TOT0 - 1), f, j);
+      first[q] = tw[(j / Sh::R2) * (N / (Sh::R0 * Sh::R1))];
+    }
+    if constexpr (THREE) {
+      constexpr int NS = Sh::R0 * Sh::R1;
+#pragma unroll
+      for (int q = 0; q < QL; ++q) {
+        int f, j;
+        fj_of<F, NBL, JF>(min(tid + q * NT, TOTL - 1), f, j);
+        last[q] = tw[(j % NS) * (N / (NS * Sh::R2))];
+      }
+    }
+  }
+};
+
+// First pass: inputs from load(f, i), radix-R0 DFT, results (times the
+// second pass's twiddles) to LDS at the Stockham position j R0 + r.  The
+// pass comes in three parts (fft_first_load: the inputs into registers;
+// fft_first_dft; fft_first_store: the LDS write) so that a caller can do
+// other work while the loads are in flight.
 template <class Sh, int F, int NT>
 struct FirstRegs {
   static constexpr int R = Sh::R0, NB = Sh::N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT;
@@ -204,73 +252,49 @@ __device__ __forceinline__ void fft_first_dft(FirstRegs<Sh, F, NT> &x) {
   for (int q = 0; q < X::Q; ++q) dft<X::R>(x.v[q]);
 }
 
-// Powers t[r] = b^r, r < R (t[0] = 1), each the product of two lower powers
-// (r = floor(r/2) + ceil(r/2)): at most log2 R products deep, so every power
-// stays within a few ulp of exp(+2 pi i r m / N) when b is a table value.
-template <int R>
-__device__ __forceinline__ void twiddle_powers(float2 b, float2 (&t)[R]) {
-  t[0] = make_float2(1.f, 0.f);
-  if constexpr (R > 1) t[1] = b;
-#pragma unroll
-  for (int r = 2; r < R; ++r) t[r] = cmul(t[r / 2], t[r - r / 2]);
-}
-
-// LDS write of the first pass; the caller synchronises before it (if buf is
-// still being read) and after.  With PRE, each output is first multiplied by
-// the twiddle that the second pass would apply to it when gathering, and the
-// second pass must then run with its twiddles off.
-template <class Sh, int F, int NT, int S, bool JF, bool PRE = false>
-__device__ __forceinline__ void fft_first_store(float2 *buf, const float2 *__restrict__ tw, int tid,
-                                                FirstRegs<Sh, F, NT> &x) {
+// LDS write of the first pass, each output multiplied by the twiddle the
+// second pass would apply to it; the caller synchronises before it (if buf is
+// still being read) and after.
+template <class Sh, int F, int NT, int S, bool JF>
+__device__ __forceinline__ void fft_first_store(float2 *buf, const TwBases<Sh, F, NT, JF> &tb,
+                                                int tid, FirstRegs<Sh, F, NT> &x) {
   using X = FirstRegs<Sh, F, NT>;
-  constexpr int N = Sh::N, PS = Sh::PS;
-  constexpr int NB1 = N / Sh::R1, NS1 = Sh::R0, TS1 = N / (Sh::R0 * Sh::R1);
+  constexpr int PS = Sh::PS;
 #pragma unroll
   for (int q = 0; q < X::Q; ++q) {
     const int idx = tid + q * NT;
     if ((X::TOT % NT) == 0 || idx < X::TOT) {
       int f, j;
       fj_of<F, X::NB, JF>(idx, f, j);
-      // output r is element r1 = p / NB1 of second-pass butterfly p % NB1
-      // (p = j R0 + r), whose twiddle exponent is ((p % NB1) mod NS1) r1 TS1:
-      // since NB1 = R0 R2, r1 = j / R2 for every r and (p % NB1) mod NS1 = r,
-      // so the R0 twiddles are the powers of tw[(j / R2) TS1]
       float2 t[X::R];
-      if constexpr (PRE) twiddle_powers<X::R>(tw[(j / Sh::R2) * TS1], t);
+      twiddle_powers<X::R>(tb.first[q], t);
 #pragma unroll
-      for (int r = 0; r < X::R; ++r) {
-        const int p = j * X::R + r;
-        if constexpr (PRE) x.v[q][r] = cmul(x.v[q][r], t[r]);
-        buf[f * S + pidx<PS>(p)] = x.v[q][r];
-      }
+      for (int r = 0; r < X::R; ++r) buf[f * S + pidx<PS>(j * X::R + r)] = cmul(x.v[q][r], t[r]);
     }
   }
 }
 
-// First pass with the second pass's twiddles applied at its store (PRE).
 template <class Sh, int F, int NT, int S, bool JF, class Load>
-__device__ __forceinline__ void fft_first(float2 *buf, const float2 *__restrict__ tw, int tid,
+__device__ __forceinline__ void fft_first(float2 *buf, const TwBases<Sh, F, NT, JF> &tb, int tid,
                                           Load load) {
   FirstRegs<Sh, F, NT> x;
   fft_first_load<Sh, F, NT, JF>(tid, load, x);
   __builtin_amdgcn_sched_barrier(0);  // every load issued before the transform starts
   fft_first_dft<Sh, F, NT>(x);
   __syncthreads();  // inputs may have come from buf
-  fft_first_store<Sh, F, NT, S, JF, true>(buf, tw, tid, x);
+  fft_first_store<Sh, F, NT, S, JF>(buf, tb, tid, x);
   __syncthreads();
 }
 
-// Loads butterfly (f, j) of a radix-R pass from LDS and applies the twiddles
-// w^(r (j mod NS)), w = exp(+2 pi i / (NS R)): the powers of the one table
-// value tw[(j mod NS) N / (NS R)] (tw[m] = exp(+2 pi i m / N)).  Every
-// element is multiplied, r = 0 included (by 1, exact up to the sign of a
-// zero).
-template <int N, int R, int NS, int S, int PS, bool TW = true>
-__device__ __forceinline__ void fft_gather(const float2 *buf, const float2 *__restrict__ tw, int f,
-                                           int j, float2 (&v)[R]) {
+// Loads butterfly (f, j) of a radix-R pass from LDS; with TW, multiplies
+// element r by base^r (every element, r = 0 included: by 1, exact up to the
+// sign of a zero).
+template <int N, int R, int S, int PS, bool TW>
+__device__ __forceinline__ void fft_gather(const float2 *buf, float2 base, int f, int j,
+                                           float2 (&v)[R]) {
   constexpr int NB = N / R;
   float2 t[R];
-  if constexpr (TW) twiddle_powers<R>(tw[(j % NS) * (N / (NS * R))], t);
+  if constexpr (TW) twiddle_powers<R>(base, t);
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = buf[f * S + pidx<PS>(j + r * NB)];
   if constexpr (TW) {
@@ -279,9 +303,9 @@ __device__ __forceinline__ void fft_gather(const float2 *buf, const float2 *__re
   }
 }
 
-// Middle pass: LDS -> LDS in place.
-template <class Sh, int R, int NS, int F, int NT, int S, bool JF, bool TW = true>
-__device__ __forceinline__ void fft_mid(float2 *buf, const float2 *__restrict__ tw, int tid) {
+// Middle pass (its twiddles were applied by the first pass): LDS -> LDS in place.
+template <class Sh, int R, int NS, int F, int NT, int S, bool JF>
+__device__ __forceinline__ void fft_mid(float2 *buf, int tid) {
   constexpr int N = Sh::N, NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT, PS = Sh::PS;
   float2 v[Q][R];
 #pragma unroll
@@ -290,7 +314,7 @@ __device__ __forceinline__ void fft_mid(float2 *buf, const float2 *__restrict__ 
     if ((TOT % NT) == 0 || idx < TOT) {
       int f, j;
       fj_of<F, NB, JF>(idx, f, j);
-      fft_gather<N, R, NS, S, PS, TW>(buf, tw, f, j, v[q]);
+      fft_gather<N, R, S, PS, false>(buf, make_float2(1.f, 0.f), f, j, v[q]);
       dft<R>(v[q]);
     }
   }
@@ -310,10 +334,11 @@ __device__ __forceinline__ void fft_mid(float2 *buf, const float2 *__restrict__ 
 }
 
 // Last pass: LDS -> registers, results handed to store(f, k, value) with k the
-// natural-order output index.
+// natural-order output index.  TW: the pass applies its own twiddles (the
+// third pass of a three-pass shape), from the thread's bases.
 template <class Sh, int R, int NS, int F, int NT, int S, bool JF, bool TW, class Store>
-__device__ __forceinline__ void fft_last(const float2 *buf, const float2 *__restrict__ tw, int tid,
-                                         Store store) {
+__device__ __forceinline__ void fft_last(const float2 *buf, const TwBases<Sh, F, NT, JF> &tb,
+                                         int tid, Store store) {
   constexpr int N = Sh::N, NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT, PS = Sh::PS;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -322,7 +347,7 @@ __device__ __forceinline__ void fft_last(const float2 *buf, const float2 *__rest
       int f, j;
       fj_of<F, NB, JF>(idx, f, j);
       float2 v[R];
-      fft_gather<N, R, NS, S, PS, TW>(buf, tw, f, j, v);
+      fft_gather<N, R, S, PS, TW>(buf, tb.last[TW ? q : 0], f, j, v);
       dft<R>(v);
       const int d0 = (j / NS) * NS * R + (j % NS);
 #pragma unroll
@@ -334,7 +359,7 @@ __device__ __forceinline__ void fft_last(const float2 *buf, const float2 *__rest
 // Last pass variant: consume(f, k0, kstep, v) receives a butterfly's R outputs
 // at natural-order indices k0 + r * kstep in increasing r (kstep = NS).
 template <class Sh, int R, int NS, int F, int NT, int S, bool JF, bool TW, class Consume>
-__device__ __forceinline__ void fft_last_block(const float2 *buf, const float2 *__restrict__ tw,
+__device__ __forceinline__ void fft_last_block(const float2 *buf, const TwBases<Sh, F, NT, JF> &tb,
                                                int tid, Consume consume) {
   constexpr int N = Sh::N, NB = N / R, TOT = F * NB, Q = (TOT + NT - 1) / NT, PS = Sh::PS;
 #pragma unroll
@@ -344,7 +369,7 @@ __device__ __forceinline__ void fft_last_block(const float2 *buf, const float2 *
       int f, j;
       fj_of<F, NB, JF>(idx, f, j);
       float2 v[R];
-      fft_gather<N, R, NS, S, PS, TW>(buf, tw, f, j, v);
+      fft_gather<N, R, S, PS, TW>(buf, tb.last[TW ? q : 0], f, j, v);
       dft<R>(v);
       consume(f, (j / NS) * NS * R + (j % NS), NS, v);
     }
@@ -352,34 +377,40 @@ __device__ __forceinline__ void fft_last_block(const float2 *buf, const float2 *
 }
 
 // The passes after the first (buf holds the first pass's output, written
-// with fft_first_store<..., PRE> and synchronised); the last pass hands whole
+// with fft_first_store and synchronised); the last pass hands whole
 // butterflies to consume.
-template <class Sh, int F, int NT, int S, bool JF, bool PRE, class Consume>
-__device__ __forceinline__ void fft_rest_blocks(float2 *buf, const float2 *__restrict__ tw,
+template <class Sh, int F, int NT, int S, bool JF, class Consume>
+__device__ __forceinline__ void fft_rest_blocks(float2 *buf, const TwBases<Sh, F, NT, JF> &tb,
                                                 int tid, Consume consume) {
   if constexpr (Sh::R2 == 1) {
-    fft_last_block<Sh, Sh::R1, Sh::R0, F, NT, S, JF, !PRE>(buf, tw, tid, consume);
+    fft_last_block<Sh, Sh::R1, Sh::R0, F, NT, S, JF, false>(buf, tb, tid, consume);
   } else {
-    fft_mid<Sh, Sh::R1, Sh::R0, F, NT, S, JF, !PRE>(buf, tw, tid);
-    fft_last_block<Sh, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF, true>(buf, tw, tid, consume);
+    fft_mid<Sh, Sh::R1, Sh::R0, F, NT, S, JF>(buf, tid);
+    fft_last_block<Sh, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF, true>(buf, tb, tid, consume);
   }
 }
 
 // Inverse (exp(+i)) unnormalised FFT of F sequences of length N: inputs from
 // load(f, i), outputs to store(f, k, value), LDS buf of F * S elements
-// (S >= Sh::PADDED) for the exchanges between passes.  The second pass's
-// twiddles are applied by the first pass's store, as in every transform here,
-// so that all of them form the same twiddle values in the same way.
+// (S >= Sh::PADDED) for the exchanges between passes; tb holds the thread's
+// twiddle bases (TwBases::load), or the second form loads them first.
+template <class Sh, int F, int NT, int S, bool JF, class Load, class Store>
+__device__ __forceinline__ void fft_inverse(float2 *buf, const TwBases<Sh, F, NT, JF> &tb,
+                                            int tid, Load load, Store store) {
+  fft_first<Sh, F, NT, S, JF>(buf, tb, tid, load);
+  if constexpr (Sh::R2 == 1) {
+    fft_last<Sh, Sh::R1, Sh::R0, F, NT, S, JF, false>(buf, tb, tid, store);
+  } else {
+    fft_mid<Sh, Sh::R1, Sh::R0, F, NT, S, JF>(buf, tid);
+    fft_last<Sh, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF, true>(buf, tb, tid, store);
+  }
+}
 template <class Sh, int F, int NT, int S, bool JF, class Load, class Store>
 __device__ __forceinline__ void fft_inverse(float2 *buf, const float2 *__restrict__ tw, int tid,
                                             Load load, Store store) {
-  fft_first<Sh, F, NT, S, JF>(buf, tw, tid, load);
-  if constexpr (Sh::R2 == 1) {
-    fft_last<Sh, Sh::R1, Sh::R0, F, NT, S, JF, false>(buf, tw, tid, store);
-  } else {
-    fft_mid<Sh, Sh::R1, Sh::R0, F, NT, S, JF, false>(buf, tw, tid);
-    fft_last<Sh, Sh::R2, Sh::R0 * Sh::R1, F, NT, S, JF, true>(buf, tw, tid, store);
-  }
+  TwBases<Sh, F, NT, JF> tb;
+  tb.load(tw, tid);
+  fft_inverse<Sh, F, NT, S, JF>(buf, tb, tid, load, store);
 }
 
 // Z value of the paired Hermitian transform at grid position (v, u), with the

@@ -324,6 +324,8 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
   const int rp = blockIdx.x % n_rp;
   const int pb0 = (blockIdx.x / n_rp) * PBW;  // first pair of this block, batch-local
   const int tid = threadIdx.x;
+  TwBases<RowFft<N>, F, NT, true> tb;  // twiddle bases of the row transforms
+  tb.load(tw, tid);
   const int r = rp_row[rp];
   const int rm = (N - r) & (N - 1);
   const bool two = rm != r;
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(RowPairCfg<N>::NT) void k_rows_pairs(
     epart[((size_t)(pb0 + tid / 2) * n_rp + rp) * 2 + (tid & 1)] = s_e[tid];
   const int sa = rp_sa[rp], sb = rp_sb[rp];
   fft_inverse<RowFft<N>, F, NT, S, true>(
-      buf, tw, tid, [&](int f, int i) { return buf[f * S + pidx<PS>(i)]; },
+      buf, tb, tid, [&](int f, int i) { return buf[f * S + pidx<PS>(i)]; },
       [&](int f, int x, float2 v) {
         const int side = f / PBW, pp = f % PBW;
         const int pl = pb0 + pp;
@@ -433,6 +435,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
   if ((b >> 3) >= per || L >= total) return;
   const int pl = L / CB, cb = L % CB;
   FirstRegs<Sh, COLS, NT> x;
+  TwBases<Sh, COLS, NT, false> tb;  // twiddle bases, loaded with the tile
   {  // rows outside the stored band read as zero through the range check
     const auto rm = buf_rsrc(M + (size_t)pl * n_rows * N + cb * COLS, (uint32_t)n_rows * N * 8u);
     fft_first_load<Sh, COLS, NT, false>(
@@ -442,6 +445,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
         },
         x);
   }
+  tb.load(tw, tid);
   float e = 0.f;  // grid energy of image a (even threads) or b (odd threads)
   {
     const auto re = buf_rsrc(epart + (size_t)pl * n_rp * 2, (uint32_t)n_rp * 8u);
@@ -459,7 +463,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
   fft_first_dft<Sh, COLS, NT>(x);
 #pragma unroll
   for (int o = 2; o < 64; o <<= 1) e += xshfl(e, xaddr(o));
-  fft_first_store<Sh, COLS, NT, S, false, true>(buf, tw, tid, x);
+  fft_first_store<Sh, COLS, NT, S, false>(buf, tb, tid, x);
   if (lane < 2) s_e[lane][wid] = e;
   __syncthreads();
   float ea = 0.f, eb = 0.f;
@@ -487,7 +491,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_cols_stats(
   int bia = 0x7fffffff, bib = 0x7fffffff;
   uint32_t ca = 0, cbn = 0;  // wave-uniform: pixels below the bracket
   uint32_t na = 0, nb = 0;   // wave-uniform: bracket members found so far
-  fft_rest_blocks<Sh, COLS, NT, S, false, true>(buf, tw, tid, [&](int f, int k0, int ks, auto &v) {
+  fft_rest_blocks<Sh, COLS, NT, S, false>(buf, tb, tid, [&](int f, int k0, int ks, auto &v) {
     constexpr int R = sizeof(v) / sizeof(v[0]);
     // Image b is computed even when the pair has no second image: its values
     // are then never used (no record is written for it and no select reads
