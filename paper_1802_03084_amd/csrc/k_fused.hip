@@ -211,36 +211,43 @@ __global__ __launch_bounds__(kDrsThreads) void k_drs(const Ein *__restrict__ vis
 // round robin), so the pair's samples stay in that XCD's L2; a batch of fewer
 // than eight pairs spreads each pair's blocks over 8 / pairs XCDs instead.
 constexpr int kCellThreads = 256;
-constexpr int kCellBlock = 1024;   // contributors staged per workgroup
+constexpr int kCellPairs = 1;      // image pairs per workgroup (2: 11.0 us, 4: 15.1 us against 9.6 us per survey batch)
 
 __global__ __launch_bounds__(kCellThreads) void k_cellsum(
     const float4 *__restrict__ vi, int nbc, int p0, int npair, int n_cells, int n_cblk,
     const int4 *__restrict__ cblk, const int32_t *__restrict__ coff,
     const int32_t *__restrict__ contrib, float4 *__restrict__ cv, int rep) {
-  __shared__ float4 val[kCellBlock];
+  constexpr int CP = kCellPairs;
+  __shared__ float4 val[CP][kCellBlock];
   const int b = blockIdx.x, xcd = b & 7, local = b >> 3;
-  int g, blk;  // image pair within the batch, cell block
-  if (rep == 1) {  // at least eight pairs: every block of a pair on one XCD
+  int g, blk;  // group of CP image pairs within the batch, cell block
+  const int ngrp = (npair + CP - 1) / CP;
+  if (rep == 1) {  // at least eight groups: every block of a group on one XCD
     g = (local / n_cblk) * 8 + xcd;
     blk = local % n_cblk;
-  } else {  // fewer pairs: `rep` XCDs share a pair's blocks
+  } else {  // fewer groups: `rep` XCDs share a group's blocks
     g = xcd / rep;
     blk = local * rep + xcd % rep;
     if (blk >= n_cblk) return;
   }
-  if (g >= npair) return;
+  if (g >= ngrp) return;
   const int tid = threadIdx.x;
-  const float4 *v = vi + (size_t)(p0 + g) * nbc;
+  // the group's pairs; a missing last pair reads the first again and is not stored
+  const float4 *v[CP];
+#pragma unroll
+  for (int c = 0; c < CP; ++c) v[c] = vi + (size_t)(p0 + min(g * CP + c, npair - 1)) * nbc;
   // the block's cells and contributor run in one load: one level of
   // dependent loads fewer before the gather
   const int4 bk = cblk[blk];
   const int c0 = bk.x, c1 = bk.y, q0 = bk.z, q1 = bk.w, nq = q1 - q0;
-  float4 *out = cv + (size_t)g * n_cells;
   auto add = [](float4 &acc, const float4 y) {
     acc.x += y.x;
     acc.y += y.y;
     acc.z += y.z;
     acc.w += y.w;
+  };
+  auto put = [&](int c, int cell, const float4 &acc) {
+    if (g * CP + c < npair) cv[(size_t)(g * CP + c) * n_cells + cell] = acc;
   };
   if (nq <= kCellBlock) {
     // stage the block's samples: every index load, then every value load, in
@@ -254,39 +261,59 @@ __global__ __launch_bounds__(kCellThreads) void k_cellsum(
     // the contributor range of this thread's first cell, fetched alongside
     const int cf = min(c0 + tid, c1 - 1);
     int f0 = coff[cf], f1 = coff[cf + 1];
-    float4 x[T];
+    float4 x[CP][T];
 #pragma unroll
-    for (int t = 0; t < T; ++t) x[t] = v[bq[t]];
+    for (int c = 0; c < CP; ++c)
 #pragma unroll
-    for (int t = 0; t < T; ++t) val[tid + t * kCellThreads] = x[t];
+      for (int t = 0; t < T; ++t) x[c][t] = v[c][bq[t]];
+#pragma unroll
+    for (int c = 0; c < CP; ++c)
+#pragma unroll
+      for (int t = 0; t < T; ++t) val[c][tid + t * kCellThreads] = x[c][t];
     asm volatile("" ::"v"(f0), "v"(f1));  // keeps the range load ahead of the barrier
     __syncthreads();
-    for (int c = c0 + tid; c < c1; c += kCellThreads) {
-      if (c != c0 + tid) {
-        f0 = coff[c];
-        f1 = coff[c + 1];
+    for (int cell = c0 + tid; cell < c1; cell += kCellThreads) {
+      if (cell != c0 + tid) {
+        f0 = coff[cell];
+        f1 = coff[cell + 1];
       }
-      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 acc[CP];
+#pragma unroll
+      for (int c = 0; c < CP; ++c) acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
       const int e = f1 - q0;
       int q = f0 - q0;
-      // four reads in flight, then the adds in contributor order
+      // four reads per pair in flight, then the adds in contributor order
       for (; q + 4 <= e; q += 4) {
-        const float4 y0 = val[q], y1 = val[q + 1], y2 = val[q + 2], y3 = val[q + 3];
-        add(acc, y0);
-        add(acc, y1);
-        add(acc, y2);
-        add(acc, y3);
+        float4 y[CP][4];
+#pragma unroll
+        for (int c = 0; c < CP; ++c)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) y[c][k] = val[c][q + k];
+#pragma unroll
+        for (int c = 0; c < CP; ++c)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) add(acc[c], y[c][k]);
       }
-      for (; q < e; ++q) add(acc, val[q]);
-      out[c] = acc;
+      for (; q < e; ++q)
+#pragma unroll
+        for (int c = 0; c < CP; ++c) add(acc[c], val[c][q]);
+#pragma unroll
+      for (int c = 0; c < CP; ++c) put(c, cell, acc[c]);
     }
   } else {
     // a cell with more contributors than a block: direct gather, same order
-    for (int c = c0 + tid; c < c1; c += kCellThreads) {
-      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-      const int e = coff[c + 1];
-      for (int q = coff[c]; q < e; ++q) add(acc, v[contrib[q]]);
-      out[c] = acc;
+    for (int cell = c0 + tid; cell < c1; cell += kCellThreads) {
+      float4 acc[CP];
+#pragma unroll
+      for (int c = 0; c < CP; ++c) acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+      const int e = coff[cell + 1];
+      for (int q = coff[cell]; q < e; ++q) {
+        const int bcq = contrib[q];
+#pragma unroll
+        for (int c = 0; c < CP; ++c) add(acc[c], v[c][bcq]);
+      }
+#pragma unroll
+      for (int c = 0; c < CP; ++c) put(c, cell, acc[c]);
     }
   }
 }
@@ -1160,11 +1187,12 @@ rf_status batch_n(const rf_plan *p, const Shape &sh, const float2 *vi, int nimg_
   float *list = (float *)(ws + B.list);
   const int npb = (pbn + sh.pbw - 1) / sh.pbw;
   const int nimg_b = std::min(2 * pbn, nimg_w - 2 * p0);  // images in this batch
-  // image pairs; with fewer than eight, several XCDs share each pair's cell
-  // blocks so that no XCD idles
+  // groups of kCellPairs image pairs; with fewer than eight, several XCDs
+  // share each group's cell blocks so that no XCD idles
   const int npair = (nimg_b + 1) / 2;
-  const int rep = npair >= 8 ? 1 : 8 / npair;
-  const int per_xcd = rep == 1 ? (npair + 7) / 8 * p->n_cblk : (p->n_cblk + rep - 1) / rep;
+  const int ngrp = (npair + kCellPairs - 1) / kCellPairs;
+  const int rep = ngrp >= 8 ? 1 : 8 / ngrp;
+  const int per_xcd = rep == 1 ? (ngrp + 7) / 8 * p->n_cblk : (p->n_cblk + rep - 1) / rep;
   RF_HIP_TRY(tm->launch(RF_K_GRID, k_cellsum, dim3(8 * per_xcd), dim3(kCellThreads), s,
                         (const float4 *)vi, p->nbl * p->nchan, p0, npair, p->n_cells,
                         p->n_cblk, p->d_cblk, p->d_ucell_off, p->d_contrib, cv, rep));

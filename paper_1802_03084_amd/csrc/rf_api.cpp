@@ -274,12 +274,12 @@ rf_status build_plan(const rf_plan_desc *d, void *d_tables, hipStream_t s, rf_pl
     zs_off.push_back((int32_t)zs_u.size());
   }
   p->n_rp = (int32_t)rp_row.size();
-  // cell blocks of at most 1024 contributors for the staged gather
+  // cell blocks of at most kCellBlock contributors for the staged gather
   std::vector<int32_t> cblk;
   for (int32_t c = 0; c < p->n_cells;) {
     cblk.push_back(c);
     int32_t e = c + 1;
-    while (e < p->n_cells && off[e + 1] - off[c] <= 1024 && e - c < 1024) ++e;
+    while (e < p->n_cells && off[e + 1] - off[c] <= kCellBlock && e - c < kCellBlock) ++e;
     c = e;
   }
   cblk.push_back(p->n_cells);

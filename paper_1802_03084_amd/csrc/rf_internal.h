@@ -9,6 +9,10 @@
 
 #include "../../include/rf.h"
 
+// Contributors per cell block of the staged gather (the host forms the
+// blocks, the gather kernel stages one block per workgroup).
+constexpr int kCellBlock = 1024;
+
 // Host-side plan object.  Immutable after rf_plan_create.
 struct rf_plan {
   // description (scalars and host copies of the arrays)
@@ -51,7 +55,7 @@ struct rf_plan {
   int32_t n_rp, n_zs;
   // cell blocks for the staged gather: block b is cells cblk[b].x ..
   // cblk[b].y - 1, whose contributors are cblk[b].z .. cblk[b].w - 1 of
-  // d_contrib, at most 1024 (a single heavier cell forms its own block)
+  // d_contrib, at most kCellBlock (a single heavier cell forms its own block)
   int32_t n_cblk;
   int4 *d_cblk;             // [n_cblk]
   double *d_freq;           // [nchan] channel centres, GHz
