@@ -31,13 +31,13 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X fp32 vector, published
 # 1024^2 images, 16 image pairs per batch), from two rocprofv3 --pmc passes
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of `bench.py --dms 2
 # --profile-only`, each scaled by what the counter reads for a 1 GiB device
-# copy (FETCH_SIZE reads 524,300 KiB for 1 GiB read: x2; WRITE_SIZE 1,049,000
+# copy (FETCH_SIZE reads 524,301 KiB for 1 GiB read: x2; WRITE_SIZE 1,048,576
 # KiB for 1 GiB written: x1).  Valid only for the kernel sources with this
 # digest (k_fused.hip, fft.h, rf_internal.h); null once they change.
-FUSED_TRAFFIC = {"digest": "07d67b06171ec643", "fetch_scale": 2.0, "write_scale": 1.0,
-                 "kib_per_dispatch": {"drs": (1439094.6, 2696010.2), "grid": (13167.0, 7362.7),
-                                      "rows": (6954.3, 113502.3), "cols": (56793.5, 1976.3),
-                                      "select": (2361.5, 0.0)}}
+FUSED_TRAFFIC = {"digest": "457b448008588b5d", "fetch_scale": 2.0, "write_scale": 1.0,
+                 "kib_per_dispatch": {"drs": (1439328.7, 2696217.4), "grid": (13128.6, 7363.6),
+                                      "rows": (6344.7, 113502.1), "cols": (56770.0, 1610.1),
+                                      "select": (2357.2, 0.0)}}
 
 
 def fused_kernel_digest():
