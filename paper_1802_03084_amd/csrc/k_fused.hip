@@ -1344,19 +1344,37 @@ rf_status segment_enqueue(const rf_plan *p, const void *vis, rf_candidate *cand,
   }
   int nbatch = 0;
   std::vector<float2 *> vi_out(p->nwidth);
-  for (int i = dm0; i < dm1; ++i) {
+  auto samples_of = [&](int i) {  // the sample buffer of DM i's parity, per width
     float2 *vi = (float2 *)(ws + L.vi[i & 1]);
     for (int j = 0; j < p->nwidth; ++j) vi_out[j] = vi + L.vi_off[j];
+  };
+  // The pass of DM i is enqueued as early as its buffer allows, right after
+  // the batches of DM i - 2 (its last readers), so that it can run while the
+  // batches of DM i - 1 do: the host enqueues a DM's batches at about the
+  // rate the device runs them, and a pass enqueued just before the batches of
+  // its own DM reached the device only when the lanes were about to wait for
+  // it.  (Running beside the batches, the pass and the batches each slow
+  // down by about the other's share: the search takes the same time either
+  // way, but no longer depends on the host keeping ahead.)
+  auto enqueue_pass = [&](int i) -> rf_status {
+    samples_of(i);
     if (!serial && i - 2 >= dm0)
       for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipStreamWaitEvent(ds, lanes->lane_dm[k][i & 1], 0));
-    st = drs_timed(p, p->d_delay + (size_t)i * p->nchan, vis, p->width.data(), p->nwidth,
-                   vi_out.data(), ds, tm);
+    const rf_status r = drs_timed(p, p->d_delay + (size_t)i * p->nchan, vis, p->width.data(),
+                                  p->nwidth, vi_out.data(), ds, tm);
+    if (r != RF_OK) return r;
+    if (!serial) RF_HIP_TRY(hipEventRecord(lanes->drs_done[i & 1], ds));
+    return RF_OK;
+  };
+  for (int i = dm0; i < std::min(dm1, dm0 + 2); ++i) {
+    st = enqueue_pass(i);
     if (st != RF_OK) return st;
-    if (!serial) {
-      RF_HIP_TRY(hipEventRecord(lanes->drs_done[i & 1], ds));
+  }
+  for (int i = dm0; i < dm1; ++i) {
+    samples_of(i);
+    if (!serial)  // the latest record of drs_done[i & 1] is DM i's pass
       for (int k = 0; k < nl; ++k)
         RF_HIP_TRY(hipStreamWaitEvent(ls[k], lanes->drs_done[i & 1], 0));
-    }
     for (int j = 0; j < p->nwidth; ++j) {
       const int w = p->width[j];
       const int nimg_w = p->nint / w;
@@ -1373,6 +1391,10 @@ rf_status segment_enqueue(const rf_plan *p, const void *vis, rf_candidate *cand,
     }
     if (!serial)
       for (int k = 0; k < nl; ++k) RF_HIP_TRY(hipEventRecord(lanes->lane_dm[k][i & 1], ls[k]));
+    if (i + 2 < dm1) {
+      st = enqueue_pass(i + 2);
+      if (st != RF_OK) return st;
+    }
     // timed serially: flush every DM; timed concurrently: only when the event
     // pool is large (a flush drains the lanes)
     if (tm->kt && (serial || tm->full())) RF_HIP_TRY(tm->flush());
