@@ -34,9 +34,9 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X fp32 vector, published
 # copy (FETCH_SIZE reads 524,301 KiB for 1 GiB read: x2; WRITE_SIZE 1,048,576
 # KiB for 1 GiB written: x1).  Valid only for the kernel sources with this
 # digest (k_fused.hip, fft.h, rf_internal.h); null once they change.
-FUSED_TRAFFIC = {"digest": "457b448008588b5d", "fetch_scale": 2.0, "write_scale": 1.0,
-                 "kib_per_dispatch": {"drs": (1439328.7, 2696217.4), "grid": (13128.6, 7363.6),
-                                      "rows": (6344.7, 113502.1), "cols": (56770.0, 1610.1),
+FUSED_TRAFFIC = {"digest": "e47b54b9a48cab4b", "fetch_scale": 2.0, "write_scale": 1.0,
+                 "kib_per_dispatch": {"drs": (1439393.6, 2696128.1), "grid": (13128.5, 7362.9),
+                                      "rows": (6346.9, 113502.1), "cols": (56770.0, 1610.1),
                                       "select": (2357.2, 0.0)}}
 
 
