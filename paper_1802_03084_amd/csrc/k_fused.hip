@@ -1133,9 +1133,12 @@ struct Lanes {
   hipStream_t lane[kMaxLanes] = {}, drs = nullptr;
   hipEvent_t start = nullptr, drs_done[2] = {}, lane_dm[kMaxLanes][2] = {},
              lane_end[kMaxLanes] = {}, drs_end = nullptr;
-  hipError_t init() {
+  // nl lane streams and the pass stream: only the streams a search uses, so
+  // that with the caller's stream they fit the device's hardware queues
+  // without two of them sharing one
+  hipError_t init(int nl) {
     hipError_t e = hipStreamCreateWithFlags(&drs, hipStreamNonBlocking);
-    for (int k = 0; k < kMaxLanes && e == hipSuccess; ++k)
+    for (int k = 0; k < std::min(nl, kMaxLanes) && e == hipSuccess; ++k)
       e = hipStreamCreateWithFlags(&lane[k], hipStreamNonBlocking);
     auto ev = [&](hipEvent_t &x) {
       if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
@@ -1485,7 +1488,7 @@ rf_status run_segment(const rf_plan *p, const void *vis, rf_candidate *cand, int
   int32_t *fb = (int32_t *)(ws + layout_of(p).fb);
   const bool serial = kt && !kt->concurrent;
   Lanes lanes;
-  if (!serial) RF_HIP_TRY(lanes.init());
+  if (!serial) RF_HIP_TRY(lanes.init(p->lanes));
   rf_status st =
       segment_enqueue(p, vis, cand, cap, ncand, stats, ws, ws_bytes, fb, s, &lanes, serial, &timer);
   if (st != RF_OK) return st;
@@ -1525,7 +1528,7 @@ rf_status segment_begin(const rf_plan *p, const void *vis, rf_candidate *cand, i
   j->ws = static_cast<char *>(ws_v);
   j->fb = (int32_t *)(j->ws + layout_of(p).fb);
   j->s = s;
-  if (j->lanes.init() != hipSuccess) {
+  if (j->lanes.init(p->lanes) != hipSuccess) {
     delete j;
     return RF_EHIP;
   }
@@ -1716,7 +1719,9 @@ rf_status batch_create(const rf_plan *const *plans, int nseg, const void *const 
     b->fb.push_back((int32_t *)(b->ws + off));
     off += align_up(((size_t)plans[i]->n_images + 1) * sizeof(int32_t));
   }
-  if (b->lanes.init() != hipSuccess) {
+  int max_lanes = 1;
+  for (int i = 0; i < nseg; ++i) max_lanes = std::max(max_lanes, (int)plans[i]->lanes);
+  if (b->lanes.init(max_lanes) != hipSuccess) {
     delete b;
     return RF_EHIP;
   }
