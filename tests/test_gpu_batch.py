@@ -92,6 +92,27 @@ def test_schedule_does_not_change_results(torch, segs):
         assert np.array_equal(st.view(np.int32), st0.view(np.int32))
 
 
+def test_batch_of_plans_with_different_lane_counts(torch, segs):
+    """A batch whose segments' plans run 1, 2, 3 and 4 lane streams (the
+    batch creates the largest number) equals the per-segment searches."""
+    import paper_1802_03084_amd as rf
+    tunings = [(1, 64), (2, 240), (3, 96), (4, 4096)]
+    try:
+        for (p, g, dv, rows0, n0, st0), t in zip(segs, tunings):
+            g.set_tuning(*t)
+        b = rf.Batch([x[1] for x in segs], [x[2] for x in segs], cap=4096, with_stats=True)
+        for rep in range(2):
+            res = b.run()
+            for (p, g, dv, rows0, n0, st0), (rows, n, st) in zip(segs, res):
+                say("lanes", g.tuning, p.name, n)
+                assert n == n0 and np.array_equal(rows, rows0), (rep, p.name)
+                assert np.array_equal(st.view(np.int32), st0.view(np.int32)), (rep, p.name)
+        b.close()
+    finally:
+        for _, g, _, _, _, _ in segs:
+            g.set_tuning(2, 240)
+
+
 def test_autotune_picks_caches_and_keeps_results(torch, segs, tmp_path):
     from paper_1802_03084_amd import autotune
     p, g, dv, rows0, n0, st0 = segs[2]
