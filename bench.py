@@ -35,7 +35,7 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X fp32 vector, published
 # KiB for 1 GiB written: x1).  Valid only for the kernel sources with this
 # digest (the device code of k_fused.hip, fft.h, rf_internal.h); null once
 # they change.
-FUSED_TRAFFIC = {"digest": "7590f956ef3fc5b7", "fetch_scale": 2.0, "write_scale": 1.0,
+FUSED_TRAFFIC = {"digest": "3f02c7c880b3bece", "fetch_scale": 2.0, "write_scale": 1.0,
                  "kib_per_dispatch": {"drs": (1439393.6, 2696128.1), "grid": (13128.5, 7362.9),
                                       "rows": (6346.9, 113502.1), "cols": (56770.0, 1610.1),
                                       "select": (2357.2, 0.0)}}
@@ -43,8 +43,10 @@ FUSED_TRAFFIC = {"digest": "7590f956ef3fc5b7", "fetch_scale": 2.0, "write_scale"
 
 def fused_kernel_digest():
     """Digest of the fused kernels' device code: k_fused.hip up to its host
-    side, fft.h and rf_internal.h (host scheduling changes keep it)."""
+    side, fft.h and rf_internal.h, without comments and blank space (host
+    scheduling and comment changes keep it)."""
     import hashlib
+    import re
     csrc = os.path.join(ROOT, "paper_1802_03084_amd", "csrc")
     h = hashlib.sha256()
     for f in ("k_fused.hip", "fft.h", "rf_internal.h"):
@@ -53,7 +55,8 @@ def fused_kernel_digest():
             cut = text.find(b"// ------------------------------------------------------------------ host side")
             assert cut > 0, "k_fused.hip: host side marker"
             text = text[:cut]
-        h.update(text)
+        text = re.sub(rb"//[^\n]*", b"", text)
+        h.update(b" ".join(text.split()))
     return h.hexdigest()[:16]
 
 

@@ -12,8 +12,9 @@
 // registers): the first pass reads its inputs from wherever the caller keeps
 // them (global memory for the column transform), the passes exchange through
 // one padded LDS buffer, and the last pass hands its outputs to the caller in
-// registers.  Twiddles come from a global table tw[m] = exp(+2 pi i m / N)
-// computed on the host in float64.
+// registers.  A butterfly's twiddles are the powers of one value of the table
+// tw[m] = exp(+2 pi i m / N) (computed on the host in float64), formed in
+// registers; each thread loads its table values once, before any barrier.
 #pragma once
 
 #include <hip/hip_runtime.h>

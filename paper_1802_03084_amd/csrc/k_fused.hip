@@ -10,7 +10,8 @@
 // pass (Parseval: sum img^2 = N^2 / W^2 * sum |H|^2 over the Hermitian part
 // H of the grid), and for noise images median|img| / rms sits within 0.2 %
 // of 0.6745.  The column pass therefore counts pixels below a bracket
-// 0.6745 rms (1 -/+ 1 %) and keeps those inside it; if the rank of the lower
+// 0.6745 rms (1 -/+ b, b from 1 % down to 0.4 % as images grow) and keeps
+// those inside it; if the rank of the lower
 // median falls inside the bracket the kept values contain it and the result
 // is exact.  Otherwise (a bright source shifts the rms, or a region of kept
 // values overflows) the image is recomputed by the step chain after the
